@@ -1,0 +1,183 @@
+"""Benchmark: one full pressure solve of the 256x256x512 bubbly duct per step.
+
+A step is the whole path on resident inputs: mixture density from the gas
+fraction, right-hand side from the face velocities, face coefficients and the
+multigrid hierarchy (pp_set_density), and the solve to a relative residual of
+1e-10 from a zero initial guess (pp_solve).  The headline form is float32
+multigrid-preconditioned CG inside float64 iterative refinement; the plain
+float64 form is timed the same way for the speed-up.
+
+Prints one JSON line (rank 0).  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-10 residual & cells·iters/s (HBM GB/s %peak); FP32-refined vs FP64; p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="duct256")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=20, help="oracle iterations in the CPU-baseline sample")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the solve is not sharded across GPUs); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_01636_amd import ppsolve, workload as W
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    case = W.preset(args.workload)
+    n = case.n_cells
+    log(f"workload {args.workload}: {case.nx}x{case.ny}x{case.nz}, {len(case.centres)} bubbles d={case.diameter}, "
+        f"void {case.alpha.mean():.4f}, generated in {time.time() - t0:.1f}s")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    alpha_t, u_t, v_t, w_t = g(case.alpha), g(case.u), g(case.v), g(case.w)
+    rho_t = torch.empty_like(alpha_t)
+    rhs_t = torch.empty_like(alpha_t)
+    p_t = torch.zeros_like(alpha_t)
+    torch.cuda.synchronize()
+
+    def step(S):
+        ppsolve.density_from_fraction(alpha_t, 1000.0, 1.2, out=rho_t)
+        ppsolve.divergence(u_t, v_t, w_t, case.h, 1.0, out=rhs_t)
+        S.set_density(rho_t)
+        p_t.zero_()
+        _, st = S.solve(rhs_t, p_t)
+        return st
+
+    results = {}
+    for mode in ("fp32_refined", "fp64"):
+        S = ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=args.tol, max_iters=4000)
+        for _ in range(args.warmup):
+            step(S)
+        torch.cuda.synchronize()
+        times, stats = [], []
+        if mode == "fp32_refined":
+            S.timing(1)
+        T0 = time.perf_counter()
+        for k in range(args.steps):
+            a = time.perf_counter()
+            st = step(S)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - a) * 1e3)
+            stats.append(st)
+        torch.cuda.synchronize()
+        T1 = time.perf_counter()
+        kt = S.timing(0) if mode == "fp32_refined" else None
+        S.timing(-1)
+        iters = [st["inner_iters_total"] if mode == "fp32_refined" else st["iters"] for st in stats]
+        results[mode] = dict(total_s=T1 - T0, times=times, stats=stats, iters=iters, kernels=kt,
+                             p=p_t.detach().cpu().numpy().copy())
+        log(f"{mode}: step ms p50 {pct(times, 50):.2f} p99 {pct(times, 99):.2f}; iters {iters[0]} "
+            f"(outer {stats[0]['outer_iters']}); residual {stats[0]['rel_residual']:.2e}; "
+            f"setup {stats[0]['setup_ms']:.2f} ms; solve {stats[0]['solve_ms']:.2f} ms")
+        S.close()
+
+    head = results["fp32_refined"]
+    ms_per_step = head["total_s"] * 1e3 / args.steps
+    iters = int(np.median(head["iters"]))
+    value = n * sum(head["iters"]) / head["total_s"]
+
+    # acceptance: the oracle's own residual of both final pressures
+    from oracle import cref, poisson as P
+    rho = P.density_from_fraction(case.alpha)
+    b = P.divergence(case.u, case.v, case.w, case.h)
+    res_ref = {m: cref.relative_residual(rho, b, results[m]["p"], case.h) for m in results}
+    diff_modes = P.relative_linf_error(results["fp32_refined"]["p"], results["fp64"]["p"])
+    log(f"oracle residual: {res_ref}; refined vs fp64 L-inf {diff_modes:.2e}")
+
+    # roofline of the dominant kernel (largest total device time among the timed finest-level kernels)
+    kt = head["kernels"] or {}
+    roof = None
+    if kt:
+        name, (ms, launches, bytes_) = max(kt.items(), key=lambda kv: kv[1][0])
+        avg_ms = ms / launches
+        achieved = bytes_ / launches / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(launches),
+                "algorithmic_bytes_per_launch": int(bytes_ / launches)}
+        kern_tab = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": int(v[1]),
+                        "GB_per_s": round(v[2] / v[1] / (v[0] / v[1] * 1e-3) / 1e9, 1),
+                        "share_of_step": round(v[0] / (head["total_s"] * 1e3), 3)} for k, v in kt.items()}
+    else:
+        kern_tab = {}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nthreads = cref.num_threads()
+        t = time.perf_counter()
+        _, it, _, secs = cref.solve(rho, b, case.h, tol=1e-30, maxit=args.cpu_iters)
+        cpu = {"value": n * it / secs, "unit": "cells*iters/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"{it} MG-preconditioned CG iterations of the float64 C/OpenMP oracle on the full "
+                         f"{case.nx}x{case.ny}x{case.nz} input ({secs:.1f} s incl. its hierarchy set-up)",
+               "host_cpu": platform.processor() or platform.machine()}
+        log(f"cpu baseline: {cpu['value']:.3e} cells*iters/s on {nthreads} threads ({time.perf_counter() - t:.1f}s)")
+
+    t64 = results["fp64"]["times"]
+    t32 = head["times"]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "cells*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"bubbly duct {case.nx}x{case.ny}x{case.nz}, {len(case.centres)} bubbles "
+                               f"d={case.diameter:g} cells, rho 1000/1.2, solve to rel. residual {args.tol:g}",
+                   "cells": n, "bubbles": len(case.centres), "form": "fp32_refined", "seed": case.seed},
+        "time_to_tol_ms": {
+            "fp32_refined": {"p50": round(pct(t32, 50), 3), "p99": round(pct(t32, 99), 3)},
+            "fp64": {"p50": round(pct(t64, 50), 3), "p99": round(pct(t64, 99), 3)},
+        },
+        "speedup_fp32_refined_vs_fp64": round(pct(t64, 50) / pct(t32, 50), 3),
+        "iters": {"fp32_refined_inner": iters, "fp32_refined_outer": head["stats"][0]["outer_iters"],
+                  "fp64": int(np.median(results["fp64"]["iters"]))},
+        "setup_ms": round(head["stats"][0]["setup_ms"], 3),
+        "oracle_rel_residual": {m: float(f"{v:.3e}") for m, v in res_ref.items()},
+        "linf_refined_vs_fp64": float(f"{diff_modes:.3e}"),
+        "cells_per_s_solved": round(n / (ms_per_step * 1e-3), 1),
+        "roofline": roof,
+        "kernels": kern_tab,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

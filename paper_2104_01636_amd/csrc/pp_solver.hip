@@ -1,0 +1,973 @@
+// pp_solver.hip -- host side of the pressure solver: hierarchy, Krylov drivers, C ABI.
+//
+// Method.  The paper solves its pressure equations with "a multigrid
+// accelerated red black SOR relaxation scheme" on the GPU (Section 2.1, after
+// eq. ppe_surface_tension) and gives no further detail.  Here the same pieces
+// -- red-black Gauss-Seidel relaxation and geometric multigrid -- precondition
+// a conjugate-gradient iteration:
+//   * finest level: flexible CG (one-term recurrence) on K p = f;
+//   * preconditioner: one multigrid cycle with red-black Gauss-Seidel
+//     (red then black before the coarse correction, black then red after),
+//     residual restriction by summing the 8 children, injection prolongation
+//     and Galerkin coarse operators (face sums);
+//   * coarse levels 1..kmax are "K-cycles": the coarse problem is solved by a
+//     few flexible-CG steps preconditioned by the next cycle; deeper levels use
+//     a plain V-cycle whose correction is scaled by wc; the coarsest level is
+//     solved with a dense inverse of K + (mean D / n) 1 1^T.
+// The preconditioner only changes the iteration count; the converged result is
+// the zero-mean solution of A p = b - mean(b).
+//
+// Mixed precision: in PP_FP32_REFINED mode the whole preconditioned Krylov
+// solve runs in float32 (dot products accumulate in float64) inside a float64
+// iterative-refinement loop: r = f - K x in float64, remove its mean, scale to
+// unit norm, solve K e = r in float32, x += s e in float64.  The outer
+// residual, the defect update and the final mean removal stay float64.
+#include "pp_kernels.hpp"
+#include "../../include/pp.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+namespace pp {
+
+static thread_local std::string g_thread_err = "no error";
+
+#define PP_HIP(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            throw Fail(PP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+        }                                                                                              \
+    } while (0)
+
+struct Fail {
+    int code;
+    std::string msg;
+    Fail(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+// ---------------------------------------------------------------- launch geometry
+
+struct Geo {
+    dim3 grid, block;
+    int kper;
+};
+
+static Geo geo(int nx, int ny, int nz, int max_blocks = kMaxRedBlocks)
+{
+    int bx = 1;
+    while (bx < nx && bx < 64) bx <<= 1;
+    int by = kBlock / bx;
+    while (by > 1 && by / 2 >= ny) by >>= 1;
+    int gx = (nx + bx - 1) / bx, gy = (ny + by - 1) / by;
+    int tiles = gx * gy;
+    int gz = std::max(1, std::min(nz, max_blocks / std::max(1, tiles)));
+    int kper = (nz + gz - 1) / gz;
+    gz = (nz + kper - 1) / kper;
+    return {dim3(gx, gy, gz), dim3(bx, by, 1), kper};
+}
+
+static dim3 lin_grid(size_t n)
+{
+    size_t b = (n + kBlock - 1) / kBlock;
+    return dim3((unsigned)std::max<size_t>(1, std::min<size_t>(b, kMaxRedBlocks)));
+}
+
+// ---------------------------------------------------------------- slots
+
+enum : int {
+    kLevSlots = 8,      // per level: ZQ, SUMZ, DQ0, DQ1, DR, RR, RSUM
+    S_ZQ = 0, S_SUMZ = 1, S_DQ0 = 2, S_DQ1 = 3, S_DR = 4, S_RR = 5, S_RSUM = 6,
+    G_BASE = 200,
+    G_BSUM = G_BASE + 0, G_BBAD = G_BASE + 1, G_FN2 = G_BASE + 2, G_TRR = G_BASE + 3, G_TRSUM = G_BASE + 4,
+    G_XSUM = G_BASE + 5, G_XBAD = G_BASE + 6, G_SCALE = G_BASE + 7, G_INVSCALE = G_BASE + 8, G_RHOSUM = G_BASE + 9,
+    G_RHOBAD = G_BASE + 10,
+    kSlots = 256
+};
+static inline int lslot(int l, int s) { return l * kLevSlots + s; }
+
+constexpr int kMaxLev = 24;
+constexpr int kDenseMax = 128;
+
+// ---------------------------------------------------------------- arena plan
+
+struct Level64 {  // float64 coefficients of a coarse level (set-up and float64 mode)
+    double *wx = nullptr, *wy = nullptr, *wz = nullptr, *invd = nullptr;
+};
+struct Level32 {
+    float *wx = nullptr, *wy = nullptr, *wz = nullptr, *invd = nullptr;
+};
+
+template <class T>
+struct Lev {
+    int nx, ny, nz;
+    size_t n;
+    LevelView<T> v;
+    bool kcyc;            // solved by K-cycle steps
+    T *rhs = nullptr, *c = nullptr, *c2 = nullptr;
+    T *xk = nullptr, *d = nullptr, *d2 = nullptr, *q = nullptr;  // Krylov levels
+};
+
+template <class T>
+struct Hier {
+    std::vector<Lev<T>> L;
+    T* Minv = nullptr;   // coarsest dense inverse (when n <= kDenseMax)
+    int nd = 0;
+};
+
+struct Params {
+    int nu0 = 1, nuc = 2, kmax = 2, kit = 2, coarse_sweeps = 16;
+    double wc = 2.0;
+    double inner_floor = 1e-5;  // refined mode: inner float32 relative tolerance floor
+    int max_outer = 40;
+};
+
+struct Handle {
+    pp_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Params prm;
+    std::string err = "no error";
+    bool have_density = false;
+
+    // geometry of levels
+    std::vector<int> lnx, lny, lnz;
+    int nlev = 0;
+
+    // arena
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+
+    // fine coefficients
+    double* rho64 = nullptr;
+    float* rho32 = nullptr;
+    double* invd64_0 = nullptr;
+    float* invd32_0 = nullptr;
+    std::vector<Level64> c64;
+    std::vector<Level32> c32;
+    double* dense_work = nullptr;
+    double* M64 = nullptr;
+    float* M32 = nullptr;
+
+    // float64 finest vectors used by both modes
+    double *f64 = nullptr, *r64 = nullptr;
+
+    Hier<double> h64;
+    Hier<float> h32;
+
+    // reductions
+    double* partials = nullptr;
+    unsigned* counter = nullptr;
+    double* slots = nullptr;
+    double* host_slots = nullptr;  // pinned
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double setup_ms = 0.0;
+
+    // optional per-kernel device timing of finest-level launches
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Pending {
+        int id;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    double kt_ms[64] = {};
+    double kt_bytes[64] = {};
+    long long kt_count[64] = {};
+};
+
+// Kernel identities for timing (finest level; float32 and float64 variants apart).
+enum KId : int {
+    KT_SMOOTH_FIRST = 0, KT_SMOOTH_HALF, KT_SMOOTH_HALF_DOT, KT_RESTRICT, KT_PROLONG_BLACK, KT_DIR_APPLY,
+    KT_UPDATE_XR, KT_TRUE_RESIDUAL, KT_N
+};
+static const char* kt_name[KT_N] = {"smooth_first", "smooth_half", "smooth_half_dots", "residual_restrict",
+                                    "prolong_black", "dir_apply", "update_xr", "true_residual"};
+
+static hipEvent_t take_event(Handle* H)
+{
+    if (H->ev_used == H->ev_pool.size()) {
+        hipEvent_t e;
+        PP_HIP(hipEventCreate(&e));
+        H->ev_pool.push_back(e);
+    }
+    return H->ev_pool[H->ev_used++];
+}
+
+// Brackets one launch with events when timing is on (id < 0: not timed).
+struct TimeScope {
+    Handle* H;
+    int id;
+    double bytes;
+    hipEvent_t a = nullptr;
+    TimeScope(Handle* h, int kid, double b) : H(h), id(kid), bytes(b)
+    {
+        if (H->timing && id >= 0) {
+            a = take_event(H);
+            PP_HIP(hipEventRecord(a, H->stream));
+        }
+    }
+    ~TimeScope()
+    {
+        if (!a) return;
+        try {
+            hipEvent_t b = take_event(H);
+            if (hipEventRecord(b, H->stream) == hipSuccess) H->pending.push_back({id, bytes, a, b});
+        } catch (...) {
+        }
+    }
+};
+
+static void collect_timing(Handle* H)
+{
+    for (auto& p : H->pending) {
+        float ms = 0.f;
+        PP_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        H->kt_ms[p.id] += ms;
+        H->kt_bytes[p.id] += p.bytes;
+        H->kt_count[p.id] += 1;
+    }
+    H->pending.clear();
+    H->ev_used = 0;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Walks the allocation plan; with base == nullptr it only counts bytes.
+struct Planner {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count)
+    {
+        size_t b = align_up(count * sizeof(T));
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += b;
+        return p;
+    }
+};
+
+static bool valid_cfg(const pp_config* cfg, std::string* why)
+{
+    if (!cfg) { if (why) *why = "null config"; return false; }
+    if (cfg->nx < 2 || cfg->ny < 2 || cfg->nz < 2) { if (why) *why = "nx, ny, nz must be >= 2"; return false; }
+    if (cfg->nz & 1) { if (why) *why = "nz must be even (red-black colouring across the periodic seam)"; return false; }
+    if (!(cfg->h > 0.0) || !std::isfinite(cfg->h)) { if (why) *why = "h must be > 0"; return false; }
+    if (!(cfg->tol > 0.0) || !std::isfinite(cfg->tol)) { if (why) *why = "tol must be > 0"; return false; }
+    if (cfg->mode != PP_FP64 && cfg->mode != PP_FP32_REFINED) { if (why) *why = "unknown mode"; return false; }
+    if ((size_t)cfg->nx * cfg->ny * cfg->nz > (size_t)1 << 31) { if (why) *why = "grid too large"; return false; }
+    {
+        Geo g = geo(cfg->nx, cfg->ny, cfg->nz);
+        if ((size_t)g.grid.x * g.grid.y * g.grid.z > (size_t)kMaxRedBlocks) {
+            if (why) *why = "cross-section too large (more than 2048 thread tiles per plane)";
+            return false;
+        }
+    }
+    return true;
+}
+
+static void levels_of(const pp_config& cfg, std::vector<int>& nx, std::vector<int>& ny, std::vector<int>& nz)
+{
+    nx = {cfg.nx};
+    ny = {cfg.ny};
+    nz = {cfg.nz};
+    while ((int)nx.size() < kMaxLev) {
+        int a = nx.back(), b = ny.back(), c = nz.back();
+        size_t n = (size_t)a * b * c;
+        if (n <= 64 || (a & 1) || (b & 1) || (c & 3)) break;
+        nx.push_back(a / 2);
+        ny.push_back(b / 2);
+        nz.push_back(c / 2);
+    }
+}
+
+// Lays out (or counts) every device array of a handle.
+static size_t plan(Handle* H, const pp_config& cfg, char* base)
+{
+    Planner P{base};
+    std::vector<int> nx, ny, nz;
+    levels_of(cfg, nx, ny, nz);
+    const int nl = (int)nx.size();
+    const bool fp64 = cfg.mode == PP_FP64;
+    const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
+    auto nn = [&](int l) { return (size_t)nx[l] * ny[l] * nz[l]; };
+    Params prm = H ? H->prm : Params{};
+
+    double* rho64 = P.take<double>(n0);
+    float* rho32 = fp64 ? nullptr : P.take<float>(n0);
+    double* invd64 = fp64 ? P.take<double>(n0) : nullptr;
+    float* invd32 = fp64 ? nullptr : P.take<float>(n0);
+    std::vector<Level64> c64(nl);
+    std::vector<Level32> c32(nl);
+    for (int l = 1; l < nl; ++l) {
+        c64[l].wx = P.take<double>(nn(l));
+        c64[l].wy = P.take<double>(nn(l));
+        c64[l].wz = P.take<double>(nn(l));
+        if (fp64) c64[l].invd = P.take<double>(nn(l));
+        if (!fp64) {
+            c32[l].wx = P.take<float>(nn(l));
+            c32[l].wy = P.take<float>(nn(l));
+            c32[l].wz = P.take<float>(nn(l));
+            c32[l].invd = P.take<float>(nn(l));
+        }
+    }
+    const size_t nd = nn(nl - 1);
+    double* dense_work = nullptr;
+    double* M64 = nullptr;
+    float* M32 = nullptr;
+    if (nl > 1 && nd <= (size_t)kDenseMax) {
+        dense_work = P.take<double>(2 * nd * nd);
+        M64 = P.take<double>(nd * nd);
+        M32 = P.take<float>(nd * nd);
+    }
+    double* f64 = P.take<double>(n0);
+    double* r64 = P.take<double>(n0);
+
+    auto make_h = [&](auto tag, auto& Hh, bool alloc) {
+        using T = decltype(tag);
+        Hh.L.assign(nl, Lev<T>{});
+        for (int l = 0; l < nl; ++l) {
+            Lev<T>& V = Hh.L[l];
+            V.nx = nx[l]; V.ny = ny[l]; V.nz = nz[l]; V.n = nn(l);
+            V.kcyc = (l >= 1 && l <= prm.kmax && l < nl - 1);
+            if (!alloc) continue;
+            if (l > 0) V.rhs = P.template take<T>(V.n);
+            V.c = P.template take<T>(V.n);
+            if (l < nl - 1) V.c2 = P.template take<T>(V.n);
+            if (l == 0 || V.kcyc) {
+                if (l > 0) V.xk = P.template take<T>(V.n);
+                V.d = P.template take<T>(V.n);
+                V.d2 = P.template take<T>(V.n);
+                V.q = P.template take<T>(V.n);
+            }
+        }
+        if (fp64) { if constexpr (std::is_same_v<T, double>) Hh.Minv = M64; }
+        else { if constexpr (std::is_same_v<T, float>) Hh.Minv = M32; }
+        Hh.nd = (nl > 1 && nd <= (size_t)kDenseMax) ? (int)nd : 0;
+    };
+    Hier<double> h64;
+    Hier<float> h32;
+    make_h(double{}, h64, fp64);
+    make_h(float{}, h32, !fp64);
+    // refined mode: the float32 finest level needs x (inner correction) and the residual
+    if (!fp64) {
+        h32.L[0].xk = P.take<float>(n0);
+        h32.L[0].rhs = P.take<float>(n0);
+    } else {
+        h64.L[0].rhs = nullptr;  // finest residual lives in r64, solution in the caller's p
+    }
+    double* partials = P.take<double>((size_t)kMaxRedBlocks * kMaxRed);
+    unsigned* counter = P.take<unsigned>(64);
+    double* slots = P.take<double>(kSlots);
+
+    if (H && base) {
+        H->lnx = nx; H->lny = ny; H->lnz = nz; H->nlev = nl;
+        H->rho64 = rho64; H->rho32 = rho32; H->invd64_0 = invd64; H->invd32_0 = invd32;
+        H->c64 = c64; H->c32 = c32;
+        H->dense_work = dense_work; H->M64 = M64; H->M32 = M32;
+        H->f64 = f64; H->r64 = r64;
+        H->partials = partials; H->counter = counter; H->slots = slots;
+        // coefficient views
+        for (int l = 0; l < nl; ++l) {
+            auto& v64 = h64.L[l].v;
+            auto& v32 = h32.L[l].v;
+            v64 = LevelView<double>{nx[l], ny[l], nz[l], nullptr, nullptr, nullptr, nullptr, nullptr};
+            v32 = LevelView<float>{nx[l], ny[l], nz[l], nullptr, nullptr, nullptr, nullptr, nullptr};
+            if (l == 0) {
+                v64.rho = rho64; v64.invd = invd64;
+                v32.rho = rho32; v32.invd = invd32;
+            } else {
+                v64.wx = c64[l].wx; v64.wy = c64[l].wy; v64.wz = c64[l].wz; v64.invd = c64[l].invd;
+                v32.wx = c32[l].wx; v32.wy = c32[l].wy; v32.wz = c32[l].wz; v32.invd = c32[l].invd;
+            }
+        }
+        H->h64 = h64;
+        H->h32 = h32;
+    }
+    return P.off;
+}
+
+// ---------------------------------------------------------------- small helpers
+
+static Reduce red(Handle* H, int s0, int s1 = 0, int s2 = 0, int s3 = 0)
+{
+    Reduce R;
+    R.partials = H->partials;
+    R.counter = H->counter;
+    R.out = H->slots;
+    R.slot[0] = s0; R.slot[1] = s1; R.slot[2] = s2; R.slot[3] = s3;
+    return R;
+}
+static Coefs coef(Handle* H, int num, int den, double sign) { return Coefs{H->slots, num, den, sign}; }
+
+static void check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Fail(PP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+static void read_slots(Handle* H, int first, int count)
+{
+    PP_HIP(hipMemcpyAsync(H->host_slots + first, H->slots + first, sizeof(double) * count, hipMemcpyDeviceToHost, H->stream));
+    PP_HIP(hipStreamSynchronize(H->stream));
+}
+
+static void write_slots(Handle* H, int first, const double* v, int count)
+{
+    for (int i = 0; i < count; ++i) H->host_slots[first + i] = v[i];
+    PP_HIP(hipMemcpyAsync(H->slots + first, H->host_slots + first, sizeof(double) * count, hipMemcpyHostToDevice, H->stream));
+}
+
+// ---------------------------------------------------------------- multigrid cycle
+
+template <class T>
+static int kid(int id) { return id + (sizeof(T) == 4 ? 0 : 32); }
+
+template <class T>
+static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int colour, int ndot, const T* q, int l)
+{
+    Geo g = geo(V.nx, V.ny, V.nz);
+    Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
+    const double sz = sizeof(T);
+    TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
+                 (double)V.n * sz * (ndot >= 2 ? 5.5 : 4.5));
+    if (fine) {
+        if (ndot == 0) k_smooth_half<T, true, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+        else if (ndot == 1) k_smooth_half<T, true, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+        else k_smooth_half<T, true, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+    } else {
+        if (ndot == 0) k_smooth_half<T, false, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+        else if (ndot == 1) k_smooth_half<T, false, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+        else k_smooth_half<T, false, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+    }
+    check_launch();
+}
+
+template <class T>
+static T* kcycle(Handle* H, Hier<T>& Hh, int l);
+
+// One multigrid cycle at level l for right-hand side f; returns the buffer holding
+// the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, reduced on the last
+// half-sweep into level l's slots.
+template <class T>
+static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const T* q)
+{
+    Lev<T>& V = Hh.L[l];
+    const bool fine = (l == 0);
+    const int last = (int)Hh.L.size() - 1;
+    if (l == last) {
+        if (l > 0 && Hh.nd > 0) {
+            k_dense_apply<T><<<1, kBlock, 0, H->stream>>>(Hh.nd, Hh.Minv, f, V.c);
+            check_launch();
+        } else {
+            // symmetric block of red-black sweeps (also the whole cycle when the
+            // finest level cannot be coarsened)
+            Geo g = geo(V.nx, V.ny, V.nz);
+            {
+                TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 4.0);
+                if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
+                else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
+            }
+            check_launch();
+            const int ns = H->prm.coarse_sweeps;
+            for (int s = 1; s < ns; ++s) {
+                smooth_half(H, V, fine, f, V.c, 0, 0, (const T*)nullptr, l);
+                smooth_half(H, V, fine, f, V.c, 1, 0, (const T*)nullptr, l);
+            }
+            for (int s = 0; s < ns; ++s) {
+                smooth_half(H, V, fine, f, V.c, 1, 0, (const T*)nullptr, l);
+                smooth_half(H, V, fine, f, V.c, 0, (s == ns - 1) ? ndot : 0, q, l);
+            }
+        }
+        return V.c;
+    }
+    const int nu = fine ? H->prm.nu0 : H->prm.nuc;
+    Geo g = geo(V.nx, V.ny, V.nz);
+    {
+        TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 4.0);
+        if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
+        else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
+    }
+    check_launch();
+    for (int s = 1; s < nu; ++s) {
+        smooth_half(H, V, fine, f, V.c, 0, 0, (const T*)nullptr, l);
+        smooth_half(H, V, fine, f, V.c, 1, 0, (const T*)nullptr, l);
+    }
+    Lev<T>& C = Hh.L[l + 1];
+    Geo gc = geo(C.nx, C.ny, C.nz);
+    {
+        TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (3.0 + 0.125));
+        if (fine) k_residual_restrict<T, true><<<gc.grid, gc.block, 0, H->stream>>>(V.v, f, V.c, C.rhs, C.nx, C.ny, C.nz, gc.kper);
+        else k_residual_restrict<T, false><<<gc.grid, gc.block, 0, H->stream>>>(V.v, f, V.c, C.rhs, C.nx, C.ny, C.nz, gc.kper);
+    }
+    check_launch();
+    T* e;
+    T wc;
+    if (C.kcyc) {
+        e = kcycle(H, Hh, l + 1);
+        wc = T(1);
+    } else {
+        e = mgcycle(H, Hh, l + 1, C.rhs, 0, (const T*)nullptr);
+        wc = (T)H->prm.wc;
+    }
+    {
+        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (5.0 + 0.125));
+        if (fine) k_prolong_black<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper);
+        else k_prolong_black<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper);
+    }
+    check_launch();
+    T* cur = V.c2;
+    for (int s = 0; s < nu; ++s) {
+        if (s > 0) smooth_half(H, V, fine, f, cur, 1, 0, (const T*)nullptr, l);
+        smooth_half(H, V, fine, f, cur, 0, (s == nu - 1) ? ndot : 0, q, l);
+    }
+    return cur;
+}
+
+template <class T>
+static void dir_apply(Handle* H, Lev<T>& V, bool fine, const T* z, int it, int l, bool mean)
+{
+    Geo g = geo(V.nx, V.ny, V.nz);
+    const int dq_prev = lslot(l, (it & 1) ? S_DQ0 : S_DQ1);
+    const int dq_cur = lslot(l, (it & 1) ? S_DQ1 : S_DQ0);
+    Coefs beta = coef(H, lslot(l, S_ZQ), dq_prev, -1.0);
+    Coefs mn = coef(H, lslot(l, S_SUMZ), -1, 1.0 / (double)V.n);
+    Reduce R = red(H, dq_cur, lslot(l, S_DR));
+    TimeScope ts(H, fine ? kid<T>(KT_DIR_APPLY) : -1, (double)V.n * sizeof(T) * (it > 0 ? 6.0 : 5.0));
+    if (fine)
+        k_dir_apply<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, g.kper, R);
+    else
+        k_dir_apply<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, g.kper, R);
+    check_launch();
+}
+
+template <class T>
+static void update_xr(Handle* H, Lev<T>& V, T* x, int it, int l, bool first, bool skip_r, bool want)
+{
+    const int dq_cur = lslot(l, (it & 1) ? S_DQ1 : S_DQ0);
+    Coefs alpha = coef(H, lslot(l, S_DR), dq_cur, 1.0);
+    TimeScope ts(H, l == 0 ? kid<T>(KT_UPDATE_XR) : -1,
+                 (double)V.n * sizeof(T) * ((first ? 1.0 : 2.0) + (skip_r ? 0.0 : 3.0)));
+    k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>(V.n, x, V.d2, V.rhs, V.q, alpha, first, skip_r, want,
+                                                         red(H, lslot(l, S_RR), lslot(l, S_RSUM)));
+    check_launch();
+}
+
+// K-cycle: kit flexible-CG steps on K_l x = rhs_l (rhs_l is used as the residual).
+template <class T>
+static T* kcycle(Handle* H, Hier<T>& Hh, int l)
+{
+    Lev<T>& V = Hh.L[l];
+    const int kit = H->prm.kit;
+    for (int it = 0; it < kit; ++it) {
+        T* z = mgcycle(H, Hh, l, V.rhs, it > 0 ? 2 : 0, V.q);
+        dir_apply(H, V, false, z, it, l, false);
+        update_xr(H, V, V.xk, it, l, it == 0, it == kit - 1, false);
+        std::swap(V.d, V.d2);
+    }
+    return V.xk;
+}
+
+// Flexible PCG on the finest level of hierarchy Hh.  V.rhs must hold the initial
+// residual; x the initial iterate (or anything when x_zero, which makes the first
+// step write x).  Runs until ||r|| <= stop * or max_it steps.  Returns steps taken.
+template <class T>
+static int fcg_finest(Handle* H, Hier<T>& Hh, T* x, bool x_zero, double rnorm_stop, int max_it, int it0, double* rnorm_out)
+{
+    Lev<T>& V = Hh.L[0];
+    int k = 0;
+    double rn = -1.0;
+    for (; k < max_it; ++k) {
+        const int it = it0 + k;
+        T* z = mgcycle(H, Hh, 0, V.rhs, k > 0 ? 2 : 1, V.q);
+        dir_apply(H, V, true, z, k, 0, true);
+        update_xr(H, V, x, k, 0, x_zero && k == 0, false, true);
+        std::swap(V.d, V.d2);
+        read_slots(H, lslot(0, S_RR), 1);
+        rn = std::sqrt(std::max(0.0, H->host_slots[lslot(0, S_RR)]));
+        (void)it;
+        if (!(rn == rn)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
+        if (rn <= rnorm_stop) { ++k; break; }
+    }
+    if (rnorm_out) *rnorm_out = rn;
+    return k;
+}
+
+// ---------------------------------------------------------------- set-up
+
+static void set_density(Handle* H, const double* rho)
+{
+    const pp_config& cfg = H->cfg;
+    const int nl = H->nlev;
+    const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
+    PP_HIP(hipEventRecord(H->ev0, H->stream));
+    // validate: finite and > 0
+    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, rho, 1, red(H, G_RHOSUM, G_RHOBAD));
+    check_launch();
+    read_slots(H, G_RHOSUM, 2);
+    if (H->host_slots[G_RHOBAD] != 0.0)
+        throw Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
+                                         " entries that are not finite or not > 0");
+    Geo g0 = geo(cfg.nx, cfg.ny, cfg.nz);
+    k_fine_setup<<<g0.grid, g0.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, rho, H->rho64, H->rho32, H->invd64_0,
+                                                      H->invd32_0, g0.kper);
+    check_launch();
+    for (int l = 1; l < nl; ++l) {
+        Geo g = geo(H->lnx[l], H->lny[l], H->lnz[l]);
+        if (l == 1)
+            k_coarsen_from_rho<<<g.grid, g.block, 0, H->stream>>>(H->lnx[0], H->lny[0], H->lnz[0], H->rho64, H->lnx[1],
+                                                                  H->lny[1], H->lnz[1], H->c64[1].wx, H->c64[1].wy,
+                                                                  H->c64[1].wz, g.kper);
+        else
+            k_coarsen_from_w<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l - 1], H->lny[l - 1], H->lnz[l - 1], H->c64[l - 1].wx,
+                                                                H->c64[l - 1].wy, H->c64[l - 1].wz, H->lnx[l], H->lny[l],
+                                                                H->lnz[l], H->c64[l].wx, H->c64[l].wy, H->c64[l].wz, g.kper);
+        check_launch();
+        k_coarse_finish<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx, H->c64[l].wy,
+                                                           H->c64[l].wz, H->c64[l].invd, H->c32[l].wx, H->c32[l].wy,
+                                                           H->c32[l].wz, H->c32[l].invd, g.kper);
+        check_launch();
+    }
+    if (H->M64) {
+        const int l = nl - 1;
+        k_dense_inverse<<<1, kBlock, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx, H->c64[l].wy,
+                                                     H->c64[l].wz, H->dense_work, H->M64, H->M32);
+        check_launch();
+    }
+    PP_HIP(hipEventRecord(H->ev1, H->stream));
+    PP_HIP(hipEventSynchronize(H->ev1));
+    float ms = 0.f;
+    PP_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1));
+    H->setup_ms = ms;
+    H->have_density = true;
+}
+
+// f = -h^2 (b - mean b); returns ||f||.
+static double prepare_rhs(Handle* H, const double* rhs)
+{
+    const pp_config& cfg = H->cfg;
+    const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
+    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, rhs, 0, red(H, G_BSUM, G_BBAD));
+    check_launch();
+    read_slots(H, G_BSUM, 2);
+    if (H->host_slots[G_BBAD] != 0.0)
+        throw Fail(PP_ERR_NONFINITE, "rhs has " + std::to_string((long long)H->host_slots[G_BBAD]) + " non-finite entries");
+    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, rhs, H->f64, -cfg.h * cfg.h, coef(H, G_BSUM, -1, 1.0 / (double)n0),
+                                                          1, red(H, G_FN2));
+    check_launch();
+    read_slots(H, G_FN2, 1);
+    return std::sqrt(H->host_slots[G_FN2]);
+}
+
+// r64 = f64 - K x in float64; returns ||r|| (sum(r) in slot G_TRSUM).
+static double true_residual(Handle* H, const double* x)
+{
+    const pp_config& cfg = H->cfg;
+    Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
+    LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->rho64, nullptr, nullptr, nullptr, nullptr};
+    TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * 32.0);
+    k_true_residual<double, true><<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, red(H, G_TRR, G_TRSUM));
+    check_launch();
+    read_slots(H, G_TRR, 2);
+    return std::sqrt(std::max(0.0, H->host_slots[G_TRR]));
+}
+
+static void remove_mean(Handle* H, double* x)
+{
+    const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
+    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, x, 0, red(H, G_XSUM, G_XBAD));
+    check_launch();
+    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, x, x, 1.0, coef(H, G_XSUM, -1, 1.0 / (double)n0), 0,
+                                                          red(H, G_FN2));
+    check_launch();
+}
+
+static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const pp_config& cfg = H->cfg;
+    const int max_it = cfg.max_iters > 0 ? cfg.max_iters : 1000;
+    const double fn = prepare_rhs(H, rhs);
+    int iters = 0, outer = 0, inner_total = 0;
+    double rel = 0.0;
+    bool converged = true;
+    if (fn == 0.0) {
+        PP_HIP(hipMemsetAsync(p, 0, sizeof(double) * (size_t)cfg.nx * cfg.ny * cfg.nz, H->stream));
+        PP_HIP(hipStreamSynchronize(H->stream));
+    } else if (cfg.mode == PP_FP64) {
+        Hier<double>& Hh = H->h64;
+        Hh.L[0].rhs = H->r64;
+        converged = false;
+        for (int restart = 0; restart < 50; ++restart) {
+            double rn = true_residual(H, p);
+            rel = rn / fn;
+            if (rel <= cfg.tol) { converged = true; break; }
+            if (iters >= max_it) break;
+            iters += fcg_finest(H, Hh, p, false, cfg.tol * fn, max_it - iters, iters, nullptr);
+        }
+        remove_mean(H, p);
+        rel = true_residual(H, p) / fn;
+        converged = converged || rel <= cfg.tol;
+    } else {
+        Hier<float>& Hh = H->h32;
+        converged = false;
+        const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
+        for (; outer < H->prm.max_outer; ++outer) {
+            double rn = true_residual(H, p);
+            rel = rn / fn;
+            if (rel <= cfg.tol) { converged = true; break; }
+            if (inner_total >= max_it) break;
+            double sc[2] = {rn, 1.0 / rn};
+            write_slots(H, G_SCALE, sc, 2);
+            k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->r64, Hh.L[0].rhs, coef(H, G_TRSUM, -1, 1.0 / (double)n0),
+                                                             coef(H, G_INVSCALE, -1, 1.0));
+            check_launch();
+            double want = std::max(H->prm.inner_floor, 0.5 * cfg.tol / rel);
+            inner_total += fcg_finest(H, Hh, Hh.L[0].xk, true, want, max_it - inner_total, inner_total, nullptr);
+            k_promote_add<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, p, Hh.L[0].xk, coef(H, G_SCALE, -1, 1.0));
+            check_launch();
+        }
+        iters = outer;
+        remove_mean(H, p);
+        rel = true_residual(H, p) / fn;
+        converged = converged || rel <= cfg.tol;
+    }
+    PP_HIP(hipStreamSynchronize(H->stream));
+    auto t1 = std::chrono::steady_clock::now();
+    if (H->timing) collect_timing(H);
+    if (st) {
+        st->iters = iters;
+        st->outer_iters = cfg.mode == PP_FP64 ? 0 : outer;
+        st->inner_iters_total = inner_total;
+        st->rel_residual = rel;
+        st->setup_ms = H->setup_ms;
+        st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        st->device_bytes = H->arena_bytes;
+    }
+    if (!converged) throw Fail(PP_ERR_NOT_CONVERGED, "not converged: relative residual " + std::to_string(rel));
+    return PP_OK;
+}
+
+static void read_env(Params& p, const pp_config* cfg = nullptr)
+{
+    if (cfg && cfg->pre_sweeps > 0) p.nu0 = cfg->pre_sweeps;
+    if (cfg && cfg->post_sweeps > 0) p.nuc = cfg->post_sweeps;
+    if (const char* s = getenv("PP_KMAX")) p.kmax = atoi(s);
+    if (const char* s = getenv("PP_KIT")) p.kit = std::max(1, atoi(s));
+    if (const char* s = getenv("PP_WC")) p.wc = atof(s);
+    if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
+    if (const char* s = getenv("PP_INNER_TOL")) p.inner_floor = atof(s);
+}
+
+}  // namespace pp
+
+// ---------------------------------------------------------------- C ABI
+
+using namespace pp;
+
+struct pp_handle_s {
+    Handle h;
+};
+
+template <class F>
+static int guarded(pp_handle h, F&& f)
+{
+    try {
+        return f();
+    } catch (const Fail& e) {
+        if (h) h->h.err = e.msg;
+        else g_thread_err = e.msg;
+        return e.code;
+    } catch (const std::exception& e) {
+        if (h) h->h.err = e.what();
+        else g_thread_err = e.what();
+        return PP_ERR_HIP;
+    }
+}
+
+extern "C" {
+
+const char* pp_version(void) { return "ppsolve 0.1 (gfx950)"; }
+
+size_t pp_footprint_bytes(const pp_config* cfg)
+{
+    if (!valid_cfg(cfg, nullptr)) return 0;
+    Handle tmp;
+    read_env(tmp.prm, cfg);
+    return plan(&tmp, *cfg, nullptr);
+}
+
+int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
+{
+    if (out) *out = nullptr;
+    std::string why;
+    if (!out) { g_thread_err = "out is null"; return PP_ERR_INVALID; }
+    if (!valid_cfg(cfg, &why)) { g_thread_err = why; return PP_ERR_INVALID; }
+    pp_handle h = new (std::nothrow) pp_handle_s;
+    if (!h) { g_thread_err = "host allocation failed"; return PP_ERR_OOM; }
+    Handle* H = &h->h;
+    H->cfg = *cfg;
+    H->stream = (hipStream_t)hip_stream;
+    read_env(H->prm, cfg);
+    int rc = guarded(nullptr, [&]() -> int {
+        PP_HIP(hipGetDevice(&H->device));
+        size_t bytes = plan(H, *cfg, nullptr);
+        if (const char* s = getenv("PP_FAULT_OOM_AT")) {
+            if ((size_t)atoll(s) <= bytes) throw Fail(PP_ERR_OOM, "injected allocation failure");
+        }
+        hipError_t e = hipMalloc((void**)&H->arena, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            H->arena = nullptr;
+            throw Fail(PP_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        H->arena_bytes = bytes;
+        plan(H, *cfg, H->arena);
+        PP_HIP(hipHostMalloc((void**)&H->host_slots, sizeof(double) * kSlots, hipHostMallocDefault));
+        PP_HIP(hipEventCreate(&H->ev0));
+        PP_HIP(hipEventCreate(&H->ev1));
+        PP_HIP(hipMemsetAsync(H->counter, 0, 64 * sizeof(unsigned), H->stream));
+        PP_HIP(hipMemsetAsync(H->slots, 0, kSlots * sizeof(double), H->stream));
+        PP_HIP(hipStreamSynchronize(H->stream));
+        return PP_OK;
+    });
+    if (rc != PP_OK) {
+        if (H->arena) (void)hipFree(H->arena);
+        if (H->host_slots) (void)hipHostFree(H->host_slots);
+        if (H->ev0) (void)hipEventDestroy(H->ev0);
+        if (H->ev1) (void)hipEventDestroy(H->ev1);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return PP_OK;
+}
+
+int pp_set_density(pp_handle h, const double* rho)
+{
+    if (!h) { g_thread_err = "null handle"; return PP_ERR_INVALID; }
+    if (!rho) { h->h.err = "rho is null"; return PP_ERR_INVALID; }
+    return guarded(h, [&]() -> int {
+        PP_HIP(hipSetDevice(h->h.device));
+        h->h.have_density = false;
+        set_density(&h->h, rho);
+        return PP_OK;
+    });
+}
+
+int pp_solve(pp_handle h, const double* rhs, double* p, pp_stats* st)
+{
+    if (!h) { g_thread_err = "null handle"; return PP_ERR_INVALID; }
+    if (!rhs || !p) { h->h.err = "rhs or p is null"; return PP_ERR_INVALID; }
+    if (!h->h.have_density) { h->h.err = "pp_solve before pp_set_density"; return PP_ERR_STATE; }
+    return guarded(h, [&]() -> int {
+        PP_HIP(hipSetDevice(h->h.device));
+        return solve(&h->h, rhs, p, st);
+    });
+}
+
+int pp_apply(pp_handle h, const double* x, double* y)
+{
+    if (!h) { g_thread_err = "null handle"; return PP_ERR_INVALID; }
+    if (!x || !y) { h->h.err = "x or y is null"; return PP_ERR_INVALID; }
+    if (!h->h.have_density) { h->h.err = "pp_apply before pp_set_density"; return PP_ERR_STATE; }
+    return guarded(h, [&]() -> int {
+        Handle* H = &h->h;
+        PP_HIP(hipSetDevice(H->device));
+        Geo g = geo(H->cfg.nx, H->cfg.ny, H->cfg.nz);
+        k_apply_a<<<g.grid, g.block, 0, H->stream>>>(H->cfg.nx, H->cfg.ny, H->cfg.nz, 1.0 / (H->cfg.h * H->cfg.h), H->rho64, x,
+                                                     y, g.kper);
+        check_launch();
+        PP_HIP(hipStreamSynchronize(H->stream));
+        return PP_OK;
+    });
+}
+
+int pp_destroy(pp_handle h)
+{
+    if (!h) return PP_OK;
+    Handle* H = &h->h;
+    (void)hipSetDevice(H->device);
+    if (H->stream) (void)hipStreamSynchronize(H->stream);
+    else (void)hipDeviceSynchronize();
+    if (H->arena) (void)hipFree(H->arena);
+    if (H->host_slots) (void)hipHostFree(H->host_slots);
+    if (H->ev0) (void)hipEventDestroy(H->ev0);
+    if (H->ev1) (void)hipEventDestroy(H->ev1);
+    for (hipEvent_t e : H->ev_pool) (void)hipEventDestroy(e);
+    delete h;
+    return PP_OK;
+}
+
+int pp_kernel_timing(pp_handle h, int mode, pp_kernel_time* out, int max_entries)
+{
+    if (!h) { g_thread_err = "null handle"; return PP_ERR_INVALID; }
+    Handle* H = &h->h;
+    if (mode == 1) {
+        for (int i = 0; i < 64; ++i) { H->kt_ms[i] = 0.0; H->kt_bytes[i] = 0.0; H->kt_count[i] = 0; }
+        H->timing = true;
+        return 0;
+    }
+    if (mode == -1) {
+        H->timing = false;
+        return 0;
+    }
+    int n = 0;
+    for (int prec = 0; prec < 2; ++prec)
+        for (int k = 0; k < KT_N; ++k) {
+            int id = k + 32 * prec;
+            if (H->kt_count[id] == 0) continue;
+            if (out && n < max_entries) {
+                std::snprintf(out[n].name, sizeof(out[n].name), "%s_%s", kt_name[k], prec ? "f64" : "f32");
+                out[n].total_ms = H->kt_ms[id];
+                out[n].launches = H->kt_count[id];
+                out[n].bytes = H->kt_bytes[id];
+            }
+            ++n;
+        }
+    return out ? std::min(n, max_entries) : n;
+}
+
+const char* pp_last_error(pp_handle h)
+{
+    if (h) return h->h.err.c_str();
+    return g_thread_err.c_str();
+}
+
+int pp_density_from_fraction(const double* a, double rho_l, double rho_g, double* rho, size_t n, void* hip_stream)
+{
+    if (!a || !rho) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
+    return guarded(nullptr, [&]() -> int {
+        if (n == 0) return PP_OK;
+        k_density<<<lin_grid(n), kBlock, 0, (hipStream_t)hip_stream>>>(n, a, rho_l, rho_g, rho);
+        check_launch();
+        PP_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+        return PP_OK;
+    });
+}
+
+int pp_divergence(int nx, int ny, int nz, double h, double dt, const double* u, const double* v, const double* w, double* out,
+                  void* hip_stream)
+{
+    if (!u || !v || !w || !out) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !(dt > 0.0)) { g_thread_err = "bad sizes, h or dt"; return PP_ERR_INVALID; }
+    return guarded(nullptr, [&]() -> int {
+        Geo g = geo(nx, ny, nz, 8192);
+        k_divergence<<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h * dt, u, v, w, out, g.kper);
+        check_launch();
+        PP_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+        return PP_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+"""The C-ABI library builds, loads and exports every declared symbol (no GPU needed)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2104_01636_amd import ppsolve
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "pp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(ppsolve.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ppsolve.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", ppsolve.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s(pp_[a-z_]+)$", out, flags=re.M))
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+    assert ppsolve.lib().pp_version().decode().startswith("ppsolve")
+
+
+def test_footprint_is_host_only_and_validates():
+    fp64 = ppsolve.footprint_bytes(256, 256, 512, "fp64")
+    fp32 = ppsolve.footprint_bytes(256, 256, 512, "fp32_refined")
+    n = 256 * 256 * 512
+    assert 60 * n < fp64 < 100 * n          # about nine float64 vectors plus coarse levels
+    assert 40 * n < fp32 < 80 * n
+    assert ppsolve.footprint_bytes(32, 32, 63) == 0     # odd nz
+    assert ppsolve.footprint_bytes(1, 32, 64) == 0      # nx < 2
+    assert ppsolve.footprint_bytes(32, 32, 64, tol=0.0) == 0
+    small = ppsolve.footprint_bytes(32, 32, 64)
+    assert small < fp64 / 100
+
+
+def test_create_rejects_bad_config_without_gpu():
+    cfg = ppsolve.make_config(32, 32, 63)
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = ppsolve.lib().pp_create(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert rc == ppsolve.PP_ERR_INVALID and not h.value
+    assert b"even" in ppsolve.lib().pp_last_error(None)

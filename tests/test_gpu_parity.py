@@ -1,0 +1,210 @@
+"""GPU path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Tolerances (float64 rounding of a 7-point stencil with 833:1 coefficient jumps):
+  * density from fraction: bit-exact (same expression, no contraction);
+  * divergence: bit-exact (same operation order);
+  * operator A x: |A_gpu x - A_ref x| <= 1e-13 * max_c sum_f |beta_f (x_nb - x_c)| / h^2;
+  * solves: relative residual computed by the oracle's own operator <= tol
+    (1e-10 float64, 1e-10 refined unless stated), pressure error vs the oracle's
+    reference solution (solved to 1e-13) < 1e-7 relative in L-infinity.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cref, poisson as P
+from paper_2104_01636_amd import ppsolve, workload as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def cpu(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def inputs(case):
+    """The same seeded (rho, b) on both sides: each side applies its own density
+    rule and divergence to the generator's gas fraction and face velocities."""
+    rho_ref = P.density_from_fraction(case.alpha)
+    b_ref = P.divergence(case.u, case.v, case.w, case.h)
+    rho_t = ppsolve.density_from_fraction(gpu(case.alpha))
+    b_t = ppsolve.divergence(gpu(case.u), gpu(case.v), gpu(case.w), case.h)
+    return rho_ref, b_ref, rho_t, b_t
+
+
+SHAPES = [(2, 2, 2), (3, 5, 4), (7, 6, 8), (16, 8, 8), (33, 17, 10), (64, 32, 32)]  # (nz, ny, nx)
+EVEN = [(2, 2, 2), (4, 5, 3), (6, 6, 8), (16, 8, 8), (34, 17, 10), (64, 32, 32)]    # solver grids: nz even
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_density_and_divergence_bit_exact(shape):
+    nz, ny, nx = shape
+    say("density/divergence", shape)
+    case = W.random_small_case(sum(shape), nx, ny, nz)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    np.testing.assert_array_equal(cpu(rho_t), rho_ref)
+    np.testing.assert_array_equal(cpu(b_t), b_ref)
+    b2 = ppsolve.divergence(gpu(case.u), gpu(case.v), gpu(case.w), case.h, dt=0.37)
+    np.testing.assert_array_equal(cpu(b2), P.divergence(case.u, case.v, case.w, case.h, 0.37))
+
+
+def op_scale(rho, x, h):
+    bx, by, bz = P.face_coefficients(rho)
+    s = np.zeros_like(x)
+    s[:, :, :-1] += np.abs(bx[:, :, :-1] * (x[:, :, 1:] - x[:, :, :-1]))
+    s[:, :-1, :] += np.abs(by[:, :-1, :] * (x[:, 1:, :] - x[:, :-1, :]))
+    s += np.abs(bz * (np.roll(x, -1, 0) - x))
+    return 2 * s.max() / h ** 2
+
+
+@pytest.mark.parametrize("shape", EVEN + [(512, 256, 256)])
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+def test_operator_matches_oracle(shape, mode):
+    nz, ny, nx = shape
+    say("apply", shape, mode)
+    if nx >= 256:
+        case = W.preset("duct256")
+    else:
+        case = W.random_small_case(3 + sum(shape), nx, ny, nz)
+    rho = P.density_from_fraction(case.alpha)
+    x = np.random.default_rng(1).standard_normal(shape)
+    with ppsolve.Solver(nx, ny, nz, case.h, mode=mode) as S:
+        S.set_density(gpu(rho))
+        y = cpu(S.apply(gpu(x)))
+    ref = cref.apply_operator(rho, x, case.h)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-13 * op_scale(rho, x, case.h))
+
+
+def check_solution(rho, b, h, p, tol, p_ref=None, linf=1e-7):
+    rr = cref.relative_residual(rho, b, p, h)
+    assert rr <= tol, f"oracle residual {rr:.3e} > {tol:.1e}"
+    assert abs(p.mean()) <= 1e-12 * np.abs(p).max()
+    if p_ref is not None:
+        err = P.relative_linf_error(p, p_ref)
+        assert err < linf, f"L-inf error {err:.3e}"
+        return rr, err
+    return rr, None
+
+
+SMALL = [(8, 4, 4), (2, 2, 2), (4, 2, 2), (12, 10, 6), (8, 6, 5), (10, 7, 9), (32, 16, 16), (64, 32, 32)]
+
+
+@pytest.mark.parametrize("shape", SMALL)
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+def test_solve_small_against_dense_or_reference(shape, mode):
+    """Tiny and ragged grids (odd sizes: no coarsening; sizes that stop coarsening
+    early: the sweep-based coarsest solve), 833:1 jumps from random gas fractions."""
+    nz, ny, nx = shape
+    say("solve small", shape, mode)
+    case = W.random_small_case(11 + sum(shape), nx, ny, nz)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    n = nx * ny * nz
+    p_ref = P.solve_dense(rho_ref, b_ref, case.h) if n <= 1024 else cref.solve(rho_ref, b_ref, case.h, tol=1e-13)[0]
+    with ppsolve.Solver(nx, ny, nz, case.h, mode=mode, tol=1e-10) as S:
+        S.set_density(rho_t)
+        p, st = S.solve(b_t)
+    p = cpu(p)
+    rr, err = check_solution(rho_ref, b_ref, case.h, p, 1e-10, p_ref)
+    say("   iters", st["iters"], st["inner_iters_total"], "res", rr, "err", err)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+def test_duct32_against_reference(mode):
+    case = W.preset("duct32")
+    say("duct32", mode)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    p_ref, it, rr_ref, _ = cref.solve(rho_ref, b_ref, case.h, tol=1e-13)
+    assert rr_ref < 1e-13
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=1e-10) as S:
+        S.set_density(rho_t)
+        p, st = S.solve(b_t)
+        p = cpu(p)
+        rr, err = check_solution(rho_ref, b_ref, case.h, p, 1e-10, p_ref)
+        say("   iters", st["iters"], st["inner_iters_total"], "res", rr, "err", err, "ms", st["solve_ms"])
+        # bitwise repeatable
+        p2, st2 = S.solve(b_t)
+        np.testing.assert_array_equal(cpu(p2), p)
+        # warm start from the solution: converges immediately
+        p3, st3 = S.solve(b_t, gpu(p))
+        assert st3["iters"] == 0
+        # a constant added to the guess does not change the answer
+        p4, _ = S.solve(b_t, gpu(p + 5.0))
+        assert P.relative_linf_error(cpu(p4), p_ref) < 1e-7 and abs(cpu(p4).mean()) < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+def test_duct128_against_reference(mode):
+    case = W.preset("duct128")
+    say("duct128", mode)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    p_ref, it, rr_ref, secs = cref.solve(rho_ref, b_ref, case.h, tol=1e-13)
+    say("   oracle", it, rr_ref, f"{secs:.1f}s")
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=1e-10) as S:
+        S.set_density(rho_t)
+        p, st = S.solve(b_t)
+    p = cpu(p)
+    rr, err = check_solution(rho_ref, b_ref, case.h, p, 1e-10, p_ref)
+    say("   iters", st["iters"], st["inner_iters_total"], "res", rr, "err", err, "ms", st["solve_ms"])
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+def test_duct256_full_size_residual(mode):
+    """256x256x512, 864 bubbles: acceptance by the oracle's residual at full size."""
+    case = W.preset("duct256")
+    say("duct256", mode)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    np.testing.assert_array_equal(cpu(rho_t), rho_ref)
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=1e-10) as S:
+        S.set_density(rho_t)
+        p, st = S.solve(b_t)
+    p = cpu(p)
+    rr, _ = check_solution(rho_ref, b_ref, case.h, p, 1e-10)
+    say("   iters", st["iters"], st["inner_iters_total"], "res", rr, "ms", st["solve_ms"], "setup", st["setup_ms"])
+
+
+def test_errors_and_degenerate_inputs():
+    say("errors")
+    nx, ny, nz = 8, 8, 16
+    case = W.random_small_case(5, nx, ny, nz)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    with ppsolve.Solver(nx, ny, nz) as S:
+        with pytest.raises(ppsolve.PPError) as e:
+            S.solve(b_t)
+        assert e.value.code == ppsolve.PP_ERR_STATE
+        bad = rho_t.clone()
+        bad[3, 2, 1] = float("nan")
+        with pytest.raises(ppsolve.PPError) as e:
+            S.set_density(bad)
+        assert e.value.code == ppsolve.PP_ERR_NONFINITE
+        bad = rho_t.clone()
+        bad[0, 0, 0] = -1.0
+        with pytest.raises(ppsolve.PPError) as e:
+            S.set_density(bad)
+        assert e.value.code == ppsolve.PP_ERR_NONFINITE
+        S.set_density(rho_t)
+        # zero and constant right-hand sides: the answer is p = 0
+        for rhs in (torch.zeros_like(b_t), torch.full_like(b_t, 3.0)):
+            p, st = S.solve(rhs, torch.ones_like(b_t))
+            assert torch.count_nonzero(p).item() == 0 and st["iters"] == 0
+        bb = b_t.clone()
+        bb[1, 1, 1] = float("inf")
+        with pytest.raises(ppsolve.PPError) as e:
+            S.solve(bb)
+        assert e.value.code == ppsolve.PP_ERR_NONFINITE
+    with ppsolve.Solver(nx, ny, nz, max_iters=1, tol=1e-14) as S:
+        S.set_density(rho_t)
+        p, st = S.solve(b_t, check=False)
+        assert st["status"] == ppsolve.PP_ERR_NOT_CONVERGED
+        assert st["iters"] == 1 and 0 < st["rel_residual"] < 1
+        assert torch.isfinite(p).all()
