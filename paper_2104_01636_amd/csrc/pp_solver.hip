@@ -113,6 +113,14 @@ struct Lev {
     bool kcyc;            // solved by K-cycle steps
     T *rhs = nullptr, *c = nullptr, *c2 = nullptr;
     T *xk = nullptr, *d = nullptr, *d2 = nullptr, *q = nullptr;  // Krylov levels
+    T *d_a = nullptr, *d_b = nullptr;  // the two search-direction buffers (d, d2 alternate between them)
+};
+
+// Event pair around one timed launch (see TimeScope).
+struct TimedPair {
+    int id;
+    double bytes;
+    hipEvent_t a, b;
 };
 
 template <class T>
@@ -120,18 +128,25 @@ struct Hier {
     std::vector<Lev<T>> L;
     T* Minv = nullptr;   // coarsest dense inverse (when n <= kDenseMax)
     int nd = 0;
+    T* x = nullptr;      // finest iterate used by the Krylov loop
+    // captured Krylov iterations: [0] first step, [1] odd steps, [2] even steps >= 2
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    std::vector<TimedPair> timed[3];  // event nodes inside each graph (timing on at capture)
 };
 
 struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 2, coarse_sweeps = 16;
     double wc = 2.0;
     double inner_floor = 1e-5;  // refined mode: inner float32 relative tolerance floor
+    bool graphs = true;
     int max_outer = 40;
 };
 
 struct Handle {
     pp_config cfg{};
-    hipStream_t stream = nullptr;
+    hipStream_t user = nullptr;    // caller's stream (may be the null stream)
+    hipStream_t stream = nullptr;  // the handle's own stream; ordered after / before `user` by events
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int device = 0;
     Params prm;
     std::string err = "no error";
@@ -171,16 +186,14 @@ struct Handle {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double setup_ms = 0.0;
 
+    bool use_graphs = true;  // replay Krylov steps from captured graphs (needs a non-null stream)
+
     // optional per-kernel device timing of finest-level launches
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    struct Pending {
-        int id;
-        double bytes;
-        hipEvent_t a, b;
-    };
-    std::vector<Pending> pending;
+    std::vector<TimedPair> pending;
+    std::vector<TimedPair>* capture_target = nullptr;  // set while capturing a graph
     double kt_ms[64] = {};
     double kt_bytes[64] = {};
     long long kt_count[64] = {};
@@ -213,6 +226,15 @@ struct TimeScope {
     TimeScope(Handle* h, int kid, double b) : H(h), id(kid), bytes(b)
     {
         if (H->timing && id >= 0) {
+            if (H->capture_target) {  // event node inside a graph being captured; owned by the graph's list
+                if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
+                if (hipEventRecord(a, H->stream) != hipSuccess) {
+                    (void)hipGetLastError();
+                    (void)hipEventDestroy(a);
+                    a = nullptr;
+                }
+                return;
+            }
             a = take_event(H);
             PP_HIP(hipEventRecord(a, H->stream));
         }
@@ -221,22 +243,35 @@ struct TimeScope {
     {
         if (!a) return;
         try {
-            hipEvent_t b = take_event(H);
-            if (hipEventRecord(b, H->stream) == hipSuccess) H->pending.push_back({id, bytes, a, b});
+            hipEvent_t b = nullptr;
+            if (H->capture_target) {
+                if (hipEventCreate(&b) != hipSuccess) return;
+            } else {
+                b = take_event(H);
+            }
+            if (hipEventRecord(b, H->stream) == hipSuccess) {
+                if (H->capture_target) H->capture_target->push_back({id, bytes, a, b});
+                else H->pending.push_back({id, bytes, a, b});
+            }
         } catch (...) {
         }
     }
 };
 
-static void collect_timing(Handle* H)
+static void accumulate(Handle* H, const std::vector<TimedPair>& v)
 {
-    for (auto& p : H->pending) {
+    for (auto& p : v) {
         float ms = 0.f;
         PP_HIP(hipEventElapsedTime(&ms, p.a, p.b));
         H->kt_ms[p.id] += ms;
         H->kt_bytes[p.id] += p.bytes;
         H->kt_count[p.id] += 1;
     }
+}
+
+static void collect_timing(Handle* H)
+{
+    accumulate(H, H->pending);
     H->pending.clear();
     H->ev_used = 0;
 }
@@ -346,8 +381,8 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
             if (l < nl - 1) V.c2 = P.template take<T>(V.n);
             if (l == 0 || V.kcyc) {
                 if (l > 0) V.xk = P.template take<T>(V.n);
-                V.d = P.template take<T>(V.n);
-                V.d2 = P.template take<T>(V.n);
+                V.d = V.d_a = P.template take<T>(V.n);
+                V.d2 = V.d_b = P.template take<T>(V.n);
                 V.q = P.template take<T>(V.n);
             }
         }
@@ -363,8 +398,10 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     if (!fp64) {
         h32.L[0].xk = P.take<float>(n0);
         h32.L[0].rhs = P.take<float>(n0);
+        h32.x = h32.L[0].xk;
     } else {
-        h64.L[0].rhs = nullptr;  // finest residual lives in r64, solution in the caller's p
+        h64.L[0].rhs = r64;           // finest residual
+        h64.x = P.take<double>(n0);   // iterate (copied from / to the caller's p)
     }
     double* partials = P.take<double>((size_t)kMaxRedBlocks * kMaxRed);
     unsigned* counter = P.take<unsigned>(64);
@@ -409,6 +446,19 @@ static Reduce red(Handle* H, int s0, int s1 = 0, int s2 = 0, int s3 = 0)
     return R;
 }
 static Coefs coef(Handle* H, int num, int den, double sign) { return Coefs{H->slots, num, den, sign}; }
+
+// Work of an entry point runs on the handle's stream, after everything queued
+// on the caller's stream before the call, and the caller's stream waits for it.
+static void enter(Handle* H)
+{
+    PP_HIP(hipEventRecord(H->ev_in, H->user));
+    PP_HIP(hipStreamWaitEvent(H->stream, H->ev_in, 0));
+}
+static void leave(Handle* H)
+{
+    PP_HIP(hipEventRecord(H->ev_out, H->stream));
+    PP_HIP(hipStreamWaitEvent(H->user, H->ev_out, 0));
+}
 
 static void check_launch()
 {
@@ -569,6 +619,8 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l)
 {
     Lev<T>& V = Hh.L[l];
     const int kit = H->prm.kit;
+    V.d = V.d_a;
+    V.d2 = V.d_b;
     for (int it = 0; it < kit; ++it) {
         T* z = mgcycle(H, Hh, l, V.rhs, it > 0 ? 2 : 0, V.q);
         dir_apply(H, V, false, z, it, l, false);
@@ -582,25 +634,96 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l)
 // residual; x the initial iterate (or anything when x_zero, which makes the first
 // step write x).  Runs until ||r|| <= stop * or max_it steps.  Returns steps taken.
 template <class T>
-static int fcg_finest(Handle* H, Hier<T>& Hh, T* x, bool x_zero, double rnorm_stop, int max_it, int it0, double* rnorm_out)
+static void fcg_step(Handle* H, Hier<T>& Hh, bool x_zero, int k)
 {
     Lev<T>& V = Hh.L[0];
+    T* z = mgcycle(H, Hh, 0, V.rhs, k > 0 ? 2 : 1, V.q);
+    dir_apply(H, V, true, z, k, 0, true);
+    update_xr(H, V, Hh.x, k, 0, x_zero && k == 0, false, true);
+    std::swap(V.d, V.d2);
+}
+
+// Flexible PCG on the finest level of hierarchy Hh.  V.rhs must hold the initial
+// residual and Hh.x the initial iterate (anything when x_zero: the first step
+// then writes x).  Runs until ||r|| <= rnorm_stop or max_it steps; returns the
+// steps taken.  Steps are replayed from captured graphs when allowed: every
+// pointer and scalar a step uses is fixed by the parity of its index.
+template <class T>
+static int fcg_finest(Handle* H, Hier<T>& Hh, bool x_zero, double rnorm_stop, int max_it, double* rnorm_out)
+{
+    Lev<T>& V = Hh.L[0];
+    V.d = V.d_a;
+    V.d2 = V.d_b;
+    const bool graphs = H->use_graphs;
     int k = 0;
     double rn = -1.0;
     for (; k < max_it; ++k) {
-        const int it = it0 + k;
-        T* z = mgcycle(H, Hh, 0, V.rhs, k > 0 ? 2 : 1, V.q);
-        dir_apply(H, V, true, z, k, 0, true);
-        update_xr(H, V, x, k, 0, x_zero && k == 0, false, true);
-        std::swap(V.d, V.d2);
+        const int kind = k == 0 ? 0 : ((k & 1) ? 1 : 2);
+        if (graphs && !Hh.exec[kind]) {
+            T* d0 = V.d;
+            T* d1 = V.d2;
+            hipGraph_t g = nullptr;
+            Hh.timed[kind].clear();
+            H->capture_target = &Hh.timed[kind];
+            hipError_t e = hipStreamBeginCapture(H->stream, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                try {
+                    fcg_step(H, Hh, x_zero, k);
+                } catch (...) {
+                    H->capture_target = nullptr;
+                    (void)hipStreamEndCapture(H->stream, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                e = hipStreamEndCapture(H->stream, &g);
+            }
+            H->capture_target = nullptr;
+            if (e == hipSuccess) e = hipGraphInstantiate(&Hh.exec[kind], g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            V.d = d0;  // capture ran nothing: restore and replay below
+            V.d2 = d1;
+            if (e != hipSuccess) {
+                // capture unavailable: run eagerly from now on
+                (void)hipGetLastError();
+                Hh.exec[kind] = nullptr;
+                H->use_graphs = false;
+                for (auto& tp : Hh.timed[kind]) {
+                    (void)hipEventDestroy(tp.a);
+                    (void)hipEventDestroy(tp.b);
+                }
+                Hh.timed[kind].clear();
+            }
+        }
+        if (H->use_graphs && Hh.exec[kind]) {
+            PP_HIP(hipGraphLaunch(Hh.exec[kind], H->stream));
+            std::swap(V.d, V.d2);
+        } else {
+            fcg_step(H, Hh, x_zero, k);
+        }
         read_slots(H, lslot(0, S_RR), 1);
+        if (H->timing && H->use_graphs && Hh.exec[kind]) accumulate(H, Hh.timed[kind]);
         rn = std::sqrt(std::max(0.0, H->host_slots[lslot(0, S_RR)]));
-        (void)it;
         if (!(rn == rn)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
         if (rn <= rnorm_stop) { ++k; break; }
     }
     if (rnorm_out) *rnorm_out = rn;
     return k;
+}
+
+template <class T>
+static void drop_graphs(Hier<T>& Hh)
+{
+    for (int i = 0; i < 3; ++i) {
+        if (Hh.exec[i]) {
+            (void)hipGraphExecDestroy(Hh.exec[i]);
+            Hh.exec[i] = nullptr;
+        }
+        for (auto& tp : Hh.timed[i]) {
+            (void)hipEventDestroy(tp.a);
+            (void)hipEventDestroy(tp.b);
+        }
+        Hh.timed[i].clear();
+    }
 }
 
 // ---------------------------------------------------------------- set-up
@@ -706,18 +829,20 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
         PP_HIP(hipStreamSynchronize(H->stream));
     } else if (cfg.mode == PP_FP64) {
         Hier<double>& Hh = H->h64;
-        Hh.L[0].rhs = H->r64;
+        const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
+        PP_HIP(hipMemcpyAsync(Hh.x, p, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
         converged = false;
         for (int restart = 0; restart < 50; ++restart) {
-            double rn = true_residual(H, p);
+            double rn = true_residual(H, Hh.x);
             rel = rn / fn;
             if (rel <= cfg.tol) { converged = true; break; }
             if (iters >= max_it) break;
-            iters += fcg_finest(H, Hh, p, false, cfg.tol * fn, max_it - iters, iters, nullptr);
+            iters += fcg_finest(H, Hh, false, cfg.tol * fn, max_it - iters, nullptr);
         }
-        remove_mean(H, p);
-        rel = true_residual(H, p) / fn;
+        remove_mean(H, Hh.x);
+        rel = true_residual(H, Hh.x) / fn;
         converged = converged || rel <= cfg.tol;
+        PP_HIP(hipMemcpyAsync(p, Hh.x, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
     } else {
         Hier<float>& Hh = H->h32;
         converged = false;
@@ -733,7 +858,7 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
                                                              coef(H, G_INVSCALE, -1, 1.0));
             check_launch();
             double want = std::max(H->prm.inner_floor, 0.5 * cfg.tol / rel);
-            inner_total += fcg_finest(H, Hh, Hh.L[0].xk, true, want, max_it - inner_total, inner_total, nullptr);
+            inner_total += fcg_finest(H, Hh, true, want, max_it - inner_total, nullptr);
             k_promote_add<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, p, Hh.L[0].xk, coef(H, G_SCALE, -1, 1.0));
             check_launch();
         }
@@ -767,6 +892,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_WC")) p.wc = atof(s);
     if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
     if (const char* s = getenv("PP_INNER_TOL")) p.inner_floor = atof(s);
+    if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
 }
 
 }  // namespace pp
@@ -817,8 +943,9 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
     if (!h) { g_thread_err = "host allocation failed"; return PP_ERR_OOM; }
     Handle* H = &h->h;
     H->cfg = *cfg;
-    H->stream = (hipStream_t)hip_stream;
+    H->user = (hipStream_t)hip_stream;
     read_env(H->prm, cfg);
+    H->use_graphs = H->prm.graphs;
     int rc = guarded(nullptr, [&]() -> int {
         PP_HIP(hipGetDevice(&H->device));
         size_t bytes = plan(H, *cfg, nullptr);
@@ -833,6 +960,9 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
         }
         H->arena_bytes = bytes;
         plan(H, *cfg, H->arena);
+        PP_HIP(hipStreamCreateWithFlags(&H->stream, hipStreamNonBlocking));
+        PP_HIP(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
+        PP_HIP(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
         PP_HIP(hipHostMalloc((void**)&H->host_slots, sizeof(double) * kSlots, hipHostMallocDefault));
         PP_HIP(hipEventCreate(&H->ev0));
         PP_HIP(hipEventCreate(&H->ev1));
@@ -842,6 +972,9 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
         return PP_OK;
     });
     if (rc != PP_OK) {
+        if (H->stream) (void)hipStreamDestroy(H->stream);
+        if (H->ev_in) (void)hipEventDestroy(H->ev_in);
+        if (H->ev_out) (void)hipEventDestroy(H->ev_out);
         if (H->arena) (void)hipFree(H->arena);
         if (H->host_slots) (void)hipHostFree(H->host_slots);
         if (H->ev0) (void)hipEventDestroy(H->ev0);
@@ -860,7 +993,9 @@ int pp_set_density(pp_handle h, const double* rho)
     return guarded(h, [&]() -> int {
         PP_HIP(hipSetDevice(h->h.device));
         h->h.have_density = false;
+        enter(&h->h);
         set_density(&h->h, rho);
+        leave(&h->h);
         return PP_OK;
     });
 }
@@ -872,7 +1007,17 @@ int pp_solve(pp_handle h, const double* rhs, double* p, pp_stats* st)
     if (!h->h.have_density) { h->h.err = "pp_solve before pp_set_density"; return PP_ERR_STATE; }
     return guarded(h, [&]() -> int {
         PP_HIP(hipSetDevice(h->h.device));
-        return solve(&h->h, rhs, p, st);
+        enter(&h->h);
+        int rc = PP_OK;
+        try {
+            rc = solve(&h->h, rhs, p, st);
+        } catch (...) {
+            (void)hipStreamSynchronize(h->h.stream);
+            leave(&h->h);
+            throw;
+        }
+        leave(&h->h);
+        return rc;
     });
 }
 
@@ -884,10 +1029,12 @@ int pp_apply(pp_handle h, const double* x, double* y)
     return guarded(h, [&]() -> int {
         Handle* H = &h->h;
         PP_HIP(hipSetDevice(H->device));
+        enter(H);
         Geo g = geo(H->cfg.nx, H->cfg.ny, H->cfg.nz);
         k_apply_a<<<g.grid, g.block, 0, H->stream>>>(H->cfg.nx, H->cfg.ny, H->cfg.nz, 1.0 / (H->cfg.h * H->cfg.h), H->rho64, x,
                                                      y, g.kper);
         check_launch();
+        leave(H);
         PP_HIP(hipStreamSynchronize(H->stream));
         return PP_OK;
     });
@@ -899,12 +1046,16 @@ int pp_destroy(pp_handle h)
     Handle* H = &h->h;
     (void)hipSetDevice(H->device);
     if (H->stream) (void)hipStreamSynchronize(H->stream);
-    else (void)hipDeviceSynchronize();
     if (H->arena) (void)hipFree(H->arena);
     if (H->host_slots) (void)hipHostFree(H->host_slots);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
     for (hipEvent_t e : H->ev_pool) (void)hipEventDestroy(e);
+    drop_graphs(H->h64);
+    drop_graphs(H->h32);
+    if (H->stream) (void)hipStreamDestroy(H->stream);
+    if (H->ev_in) (void)hipEventDestroy(H->ev_in);
+    if (H->ev_out) (void)hipEventDestroy(H->ev_out);
     delete h;
     return PP_OK;
 }
@@ -913,13 +1064,14 @@ int pp_kernel_timing(pp_handle h, int mode, pp_kernel_time* out, int max_entries
 {
     if (!h) { g_thread_err = "null handle"; return PP_ERR_INVALID; }
     Handle* H = &h->h;
-    if (mode == 1) {
-        for (int i = 0; i < 64; ++i) { H->kt_ms[i] = 0.0; H->kt_bytes[i] = 0.0; H->kt_count[i] = 0; }
-        H->timing = true;
-        return 0;
-    }
-    if (mode == -1) {
-        H->timing = false;
+    if (mode == 1 || mode == -1) {
+        // graphs are recaptured with (or without) event nodes on their next use
+        (void)hipStreamSynchronize(H->stream);
+        drop_graphs(H->h64);
+        drop_graphs(H->h32);
+        if (mode == 1)
+            for (int i = 0; i < 64; ++i) { H->kt_ms[i] = 0.0; H->kt_bytes[i] = 0.0; H->kt_count[i] = 0; }
+        H->timing = mode == 1;
         return 0;
     }
     int n = 0;
