@@ -40,6 +40,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle iterations in the CPU-baseline sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for hardware traffic counters)")
+    ap.add_argument("--forms", default="fp32_refined,fp64")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the solve is not sharded across GPUs); use --gpus 1",
@@ -74,15 +77,24 @@ def main():
         _, st = S.solve(rhs_t, p_t)
         return st
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 2 x 1 GiB device-to-device copies (read 1 GiB + write 1 GiB each)")
+        del src, dst
+
     results = {}
-    for mode in ("fp32_refined", "fp64"):
+    forms = args.forms.split(",")
+    for mode in forms:
         S = ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=args.tol, max_iters=4000)
         for _ in range(args.warmup):
             step(S)
         torch.cuda.synchronize()
         times, stats = [], []
-        if mode == "fp32_refined":
-            S.timing(1)
+        S.timing(1)
         T0 = time.perf_counter()
         for k in range(args.steps):
             a = time.perf_counter()
@@ -92,7 +104,7 @@ def main():
             stats.append(st)
         torch.cuda.synchronize()
         T1 = time.perf_counter()
-        kt = S.timing(0) if mode == "fp32_refined" else None
+        kt = S.timing(0)
         S.timing(-1)
         iters = [st["inner_iters_total"] if mode == "fp32_refined" else st["iters"] for st in stats]
         results[mode] = dict(total_s=T1 - T0, times=times, stats=stats, iters=iters, kernels=kt,
@@ -102,15 +114,17 @@ def main():
             f"setup {stats[0]['setup_ms']:.2f} ms; solve {stats[0]['solve_ms']:.2f} ms")
         S.close()
 
-    head = results["fp32_refined"]
+    head = results[forms[0]]
     ms_per_step = head["total_s"] * 1e3 / args.steps
     iters = int(np.median(head["iters"]))
     value = n * sum(head["iters"]) / head["total_s"]
 
     # agreement of the two forms (both zero-mean)
-    pa, pb = results["fp32_refined"]["p"], results["fp64"]["p"]
-    diff_modes = float(np.max(np.abs(pa - pb)) / np.max(np.abs(pb)))
-    log(f"refined vs fp64 L-inf {diff_modes:.2e}")
+    diff_modes = None
+    if "fp32_refined" in results and "fp64" in results:
+        pa, pb = results["fp32_refined"]["p"], results["fp64"]["p"]
+        diff_modes = float(np.max(np.abs(pa - pb)) / np.max(np.abs(pb)))
+        log(f"refined vs fp64 L-inf {diff_modes:.2e}")
 
     # roofline of the dominant kernel (largest total device time among the timed finest-level kernels)
     kt = head["kernels"] or {}
@@ -144,8 +158,7 @@ def main():
                "host_cpu": platform.processor() or platform.machine()}
         log(f"cpu baseline: {cpu['value']:.3e} cells*iters/s on {nthreads} threads ({time.perf_counter() - t:.1f}s)")
 
-    t64 = results["fp64"]["times"]
-    t32 = head["times"]
+    tt = {m: results[m]["times"] for m in results}
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -161,17 +174,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"bubbly duct {case.nx}x{case.ny}x{case.nz}, {len(case.centres)} bubbles "
                                f"d={case.diameter:g} cells, rho 1000/1.2, solve to rel. residual {args.tol:g}",
-                   "cells": n, "bubbles": len(case.centres), "form": "fp32_refined", "seed": case.seed},
-        "time_to_tol_ms": {
-            "fp32_refined": {"p50": round(pct(t32, 50), 3), "p99": round(pct(t32, 99), 3)},
-            "fp64": {"p50": round(pct(t64, 50), 3), "p99": round(pct(t64, 99), 3)},
-        },
-        "speedup_fp32_refined_vs_fp64": round(pct(t64, 50) / pct(t32, 50), 3),
-        "iters": {"fp32_refined_inner": iters, "fp32_refined_outer": head["stats"][0]["outer_iters"],
-                  "fp64": int(np.median(results["fp64"]["iters"]))},
+                   "cells": n, "bubbles": len(case.centres), "form": forms[0], "seed": case.seed},
+        "time_to_tol_ms": {m: {"p50": round(pct(t, 50), 3), "p99": round(pct(t, 99), 3)} for m, t in tt.items()},
+        "speedup_fp32_refined_vs_fp64": (round(pct(tt["fp64"], 50) / pct(tt["fp32_refined"], 50), 3)
+                                         if "fp64" in tt and "fp32_refined" in tt else None),
+        "iters": {m: {"krylov": int(np.median(results[m]["iters"])),
+                      "outer": int(results[m]["stats"][0]["outer_iters"])} for m in results},
         "setup_ms": round(head["stats"][0]["setup_ms"], 3),
         "rel_residual": {m: float(f"{results[m]['stats'][-1]['rel_residual']:.3e}") for m in results},
-        "linf_refined_vs_fp64": float(f"{diff_modes:.3e}"),
+        "linf_refined_vs_fp64": float(f"{diff_modes:.3e}") if diff_modes is not None else None,
         "cells_per_s_solved": round(n / (ms_per_step * 1e-3), 1),
         "roofline": roof,
         "kernels": kern_tab,

@@ -119,6 +119,25 @@ int pp_density_from_fraction(const double* a, double rho_l, double rho_g, double
 int pp_divergence(int nx, int ny, int nz, double h, double dt, const double* u, const double* v, const double* w,
                   double* out, void* hip_stream);
 
+/* Projection of the face velocities (step 12 of Section 2.2, on faces), in
+ * place: u_f -= dt * beta_f * (p_R - p_L) / h for every face, beta_f from rho;
+ * the wall entries (i = nx-1 of u, j = ny-1 of v) are set to zero.  With p
+ * from pp_solve for rhs = div(u)/dt, div(u_new) = dt * (residual of the
+ * solve).  rho, p, u, v, w: device, N values each. */
+int pp_project(int nx, int ny, int nz, double h, double dt, const double* rho, const double* p, double* u, double* v,
+               double* w, void* hip_stream);
+
+/* Right-hand side of the surface-tension pressure equation (Section 2.1,
+ * eq. ppe_surface_tension with the interface force of eq. jump_condition as
+ * its source, applied at faces): out = div(beta f) with the face force
+ * f = sigma * (kappa_L + kappa_R)/2 * (a_R - a_L) / h, a the gas fraction and
+ * kappa the cell curvature (positive for a bubble).  Solving A p = out with
+ * pp_solve gives the pressure that balances f (higher inside the gas); for a
+ * constant curvature it is sigma * kappa * (a - mean a).  Device arrays of N
+ * values; wall faces carry no force. */
+int pp_surface_tension_rhs(int nx, int ny, int nz, double h, double sigma, const double* rho, const double* alpha,
+                           const double* kappa, double* out, void* hip_stream);
+
 /* Device time of the finest-level kernels, measured with HIP events on the
  * handle's stream around each launch.
  *   mode = 1: clear the counters and start timing;

@@ -186,3 +186,41 @@ def manufactured(nx, ny, nz, h):
     drx, dry, drz = -np.pi * sx * sz, 0.0 * x, kz * cx * cz
     f = lap / rho - (drx * dpx + dry * dpy + drz * dpz) / rho ** 2
     return rho, remove_mean(f), remove_mean(p)
+
+
+def project(rho, p, u, v, w, h, dt=1.0):
+    """Face-velocity correction of the projection (Section 2.2, step 12, on faces):
+    u_f <- u_f - dt * beta_f * (grad p)_f; wall faces stay zero."""
+    bx, by, bz = face_coefficients(rho)
+    gx, gy, gz = gradient(p, h)
+    un = np.array(u, dtype=np.float64, copy=True) - dt * (bx * gx)
+    vn = np.array(v, dtype=np.float64, copy=True) - dt * (by * gy)
+    wn = np.asarray(w, dtype=np.float64) - dt * (bz * gz)
+    un[:, :, -1] = 0.0
+    vn[:, -1, :] = 0.0
+    return un, vn, wn
+
+
+def surface_force(alpha_gas, kappa, sigma, h):
+    """Sharp-surface-force face values (Section 2.1, eq. jump_condition, with the
+    jump applied at faces): f_f = sigma * kappa_f * (a_R - a_L) / h, kappa_f the
+    linear average of the cell curvatures; zero on wall faces.  With this sign the
+    balancing pressure is higher inside the gas (p = sigma kappa a for constant kappa)."""
+    a = np.asarray(alpha_gas, dtype=np.float64)
+    k = np.broadcast_to(np.asarray(kappa, dtype=np.float64), a.shape)
+    fx = np.zeros_like(a)
+    fy = np.zeros_like(a)
+    fx[:, :, :-1] = sigma * (0.5 * (k[:, :, :-1] + k[:, :, 1:])) * ((a[:, :, 1:] - a[:, :, :-1]) / h)
+    fy[:, :-1, :] = sigma * (0.5 * (k[:, :-1, :] + k[:, 1:, :])) * ((a[:, 1:, :] - a[:, :-1, :]) / h)
+    kn = np.roll(k, -1, axis=0)
+    fz = sigma * (0.5 * (k + kn)) * ((np.roll(a, -1, axis=0) - a) / h)
+    return fx, fy, fz
+
+
+def surface_tension_rhs(rho, alpha_gas, kappa, sigma, h):
+    """Right-hand side of the surface-tension pressure equation (Section 2.1,
+    eq. ppe_surface_tension with eq. jump_condition as the source):
+    div(beta grad p~) = div(beta f)."""
+    bx, by, bz = face_coefficients(rho)
+    fx, fy, fz = surface_force(alpha_gas, kappa, sigma, h)
+    return divergence(bx * fx, by * fy, bz * fz, h)

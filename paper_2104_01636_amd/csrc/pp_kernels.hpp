@@ -633,4 +633,56 @@ __global__ void __launch_bounds__(kBlock) k_apply_a(int nx, int ny, int nz, doub
     }
 }
 
+// Projection on faces (step 12 restricted to face velocities), in place:
+// u_f -= dt * beta_f * (p_R - p_L)/h; wall faces set to zero.
+__global__ void __launch_bounds__(kBlock) k_project(int nx, int ny, int nz, double h, double dt, const double* __restrict__ rho,
+                                                   const double* __restrict__ p, double* u, double* v, double* w, int kper)
+{
+#pragma clang fp contract(off)
+    Tile t = tile(nx, ny, nz, kper);
+    if (!t.act) return;
+    const size_t sy = nx, sz = (size_t)nx * ny;
+    for (int k = t.k0; k < t.k1; ++k) {
+        size_t c = cell(nx, ny, t.i, t.j, k);
+        size_t ct = k < nz - 1 ? c + sz : c - (size_t)(nz - 1) * sz;
+        const double rc = rho[c], pc = p[c];
+        u[c] = t.i < nx - 1 ? u[c] - dt * ((2.0 / (rc + rho[c + 1])) * ((p[c + 1] - pc) / h)) : 0.0;
+        v[c] = t.j < ny - 1 ? v[c] - dt * ((2.0 / (rc + rho[c + sy])) * ((p[c + sy] - pc) / h)) : 0.0;
+        w[c] = w[c] - dt * ((2.0 / (rc + rho[ct])) * ((p[ct] - pc) / h));
+    }
+}
+
+// Right-hand side of the surface-tension pressure equation: out = div(beta f)
+// with the face force f = sigma * (kappa_L + kappa_R)/2 * (a_R - a_L)/h.
+__device__ inline double st_flux(const double* rho, const double* a, const double* kap, double sigma, double h, size_t L,
+                                 size_t R)
+{
+#pragma clang fp contract(off)
+    const double beta = 2.0 / (rho[L] + rho[R]);
+    const double f = sigma * (0.5 * (kap[L] + kap[R])) * ((a[R] - a[L]) / h);
+    return beta * f;
+}
+
+__global__ void __launch_bounds__(kBlock) k_surface_rhs(int nx, int ny, int nz, double h, double sigma,
+                                                       const double* __restrict__ rho, const double* __restrict__ a,
+                                                       const double* __restrict__ kap, double* __restrict__ out, int kper)
+{
+#pragma clang fp contract(off)
+    Tile t = tile(nx, ny, nz, kper);
+    if (!t.act) return;
+    const size_t sy = nx, sz = (size_t)nx * ny;
+    for (int k = t.k0; k < t.k1; ++k) {
+        size_t c = cell(nx, ny, t.i, t.j, k);
+        size_t ct = k < nz - 1 ? c + sz : c - (size_t)(nz - 1) * sz;
+        size_t cb = k > 0 ? c - sz : c + (size_t)(nz - 1) * sz;
+        double fe = t.i < nx - 1 ? st_flux(rho, a, kap, sigma, h, c, c + 1) : 0.0;
+        double fw = t.i > 0 ? st_flux(rho, a, kap, sigma, h, c - 1, c) : 0.0;
+        double fn = t.j < ny - 1 ? st_flux(rho, a, kap, sigma, h, c, c + sy) : 0.0;
+        double fs = t.j > 0 ? st_flux(rho, a, kap, sigma, h, c - sy, c) : 0.0;
+        double ft = st_flux(rho, a, kap, sigma, h, c, ct);
+        double fb = st_flux(rho, a, kap, sigma, h, cb, c);
+        out[c] = (((fe - fw) + (fn - fs)) + (ft - fb)) / h;
+    }
+}
+
 }  // namespace pp

@@ -1122,4 +1122,32 @@ int pp_divergence(int nx, int ny, int nz, double h, double dt, const double* u, 
     });
 }
 
+int pp_project(int nx, int ny, int nz, double h, double dt, const double* rho, const double* p, double* u, double* v, double* w,
+               void* hip_stream)
+{
+    if (!rho || !p || !u || !v || !w) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !(dt > 0.0)) { g_thread_err = "bad sizes, h or dt"; return PP_ERR_INVALID; }
+    return guarded(nullptr, [&]() -> int {
+        Geo g = geo(nx, ny, nz, 8192);
+        k_project<<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h, dt, rho, p, u, v, w, g.kper);
+        check_launch();
+        PP_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+        return PP_OK;
+    });
+}
+
+int pp_surface_tension_rhs(int nx, int ny, int nz, double h, double sigma, const double* rho, const double* alpha,
+                           const double* kappa, double* out, void* hip_stream)
+{
+    if (!rho || !alpha || !kappa || !out) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0)) { g_thread_err = "bad sizes or h"; return PP_ERR_INVALID; }
+    return guarded(nullptr, [&]() -> int {
+        Geo g = geo(nx, ny, nz, 8192);
+        k_surface_rhs<<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h, sigma, rho, alpha, kappa, out, g.kper);
+        check_launch();
+        PP_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+        return PP_OK;
+    });
+}
+
 }  // extern "C"

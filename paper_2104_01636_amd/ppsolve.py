@@ -29,7 +29,8 @@ MODES = {"fp64": 0, "fp32_refined": 1}
 
 # Every entry point declared in include/pp.h.
 EXPORTS = ("pp_footprint_bytes", "pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_destroy",
-           "pp_last_error", "pp_density_from_fraction", "pp_divergence", "pp_kernel_timing", "pp_version")
+           "pp_last_error", "pp_density_from_fraction", "pp_divergence", "pp_project", "pp_surface_tension_rhs",
+           "pp_kernel_timing", "pp_version")
 
 
 class PPError(RuntimeError):
@@ -82,10 +83,12 @@ def lib():
         L.pp_density_from_fraction.argtypes = [vp, cd, cd, vp, sz, vp]
         L.pp_divergence.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp]
         L.pp_version.restype = ctypes.c_char_p
+        L.pp_project.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp, vp]
+        L.pp_surface_tension_rhs.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp]
         L.pp_kernel_timing.argtypes = [vp, ci, ctypes.POINTER(KernelTime), ci]
         L.pp_kernel_timing.restype = ci
         for name in ("pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_destroy",
-                     "pp_density_from_fraction", "pp_divergence"):
+                     "pp_density_from_fraction", "pp_divergence", "pp_project", "pp_surface_tension_rhs"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -198,6 +201,27 @@ def divergence(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, h: float, dt: 
     out = torch.empty_like(u) if out is None else out
     _check(lib().pp_divergence(nx, ny, nz, float(h), float(dt), _dev(u, n, "u"), _dev(v, n, "v"), _dev(w, n, "w"),
                                _dev(out, n, "out"), _stream_ptr(stream)))
+    return out
+
+
+def project(rho: torch.Tensor, p: torch.Tensor, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, h: float,
+            dt: float = 1.0, stream=None):
+    """In place: u, v, w -= dt * beta_f * grad(p) on faces (wall faces zeroed)."""
+    nz, ny, nx = u.shape
+    n = u.numel()
+    _check(lib().pp_project(nx, ny, nz, float(h), float(dt), _dev(rho, n, "rho"), _dev(p, n, "p"), _dev(u, n, "u"),
+                            _dev(v, n, "v"), _dev(w, n, "w"), _stream_ptr(stream)))
+    return u, v, w
+
+
+def surface_tension_rhs(rho: torch.Tensor, alpha: torch.Tensor, kappa: torch.Tensor, sigma: float, h: float, out=None,
+                        stream=None):
+    nz, ny, nx = rho.shape
+    n = rho.numel()
+    out = torch.empty_like(rho) if out is None else out
+    _check(lib().pp_surface_tension_rhs(nx, ny, nz, float(h), float(sigma), _dev(rho, n, "rho"),
+                                        _dev(alpha, n, "alpha"), _dev(kappa, n, "kappa"), _dev(out, n, "out"),
+                                        _stream_ptr(stream)))
     return out
 
 

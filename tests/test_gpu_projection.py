@@ -1,0 +1,83 @@
+"""Steps around the solve on the GPU: face projection and the surface-tension pressure.
+
+* projection (step 12 on faces): bit-exact against the oracle for the same
+  pressure; after a solve of step 11 the projected velocity's divergence is
+  dt times the solve's residual.
+* surface tension (eq. ppe_surface_tension with eq. jump_condition as source):
+  the right-hand side is bit-exact against the oracle; for a static bubble with
+  exact (constant) curvature the solved pressure is sigma*kappa*(a - mean a) and
+  the face velocity it leaves is zero to rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cref, poisson as P
+from paper_2104_01636_amd import ppsolve, workload as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def c(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["duct32", "duct128"])
+def test_projection_removes_divergence(name):
+    print("projection", name, flush=True)
+    case = W.preset(name)
+    dt = 0.5
+    rho_t = ppsolve.density_from_fraction(g(case.alpha))
+    u_t, v_t, w_t = g(case.u), g(case.v), g(case.w)
+    b_t = ppsolve.divergence(u_t, v_t, w_t, case.h, dt)
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, tol=1e-12) as S:
+        S.set_density(rho_t)
+        p_t, st = S.solve(b_t)
+    p = c(p_t)
+    rho = P.density_from_fraction(case.alpha)
+    un, vn, wn = P.project(rho, p, case.u, case.v, case.w, case.h, dt)
+    ppsolve.project(rho_t, p_t, u_t, v_t, w_t, case.h, dt)
+    np.testing.assert_array_equal(c(u_t), un)
+    np.testing.assert_array_equal(c(v_t), vn)
+    np.testing.assert_array_equal(c(w_t), wn)
+    d_new = c(ppsolve.divergence(u_t, v_t, w_t, case.h))
+    b = P.divergence(case.u, case.v, case.w, case.h, dt)
+    assert np.max(np.abs(d_new - d_new.mean())) < 1e-9 * np.max(np.abs(b))
+    print("   max |div u_new| / max |div u| =", np.max(np.abs(d_new)) / np.max(np.abs(b)), flush=True)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+def test_static_bubble_surface_tension_balance(mode):
+    print("static bubble", mode, flush=True)
+    nx, ny, nz = 48, 48, 64
+    h = 1.0 / nx
+    R = 9.5
+    a = W.volume_fraction(nx, ny, nz, np.array([[24.3, 23.6, 31.1]]), 2 * R)
+    rho = P.density_from_fraction(a)
+    sigma, kappa = 0.072, 2.0 / (R * h)
+    kap = np.full(a.shape, kappa)
+    rhs_ref = P.surface_tension_rhs(rho, a, kappa, sigma, h)
+    rho_t, a_t, k_t = g(rho), g(a), g(kap)
+    rhs_t = ppsolve.surface_tension_rhs(rho_t, a_t, k_t, sigma, h)
+    np.testing.assert_array_equal(c(rhs_t), rhs_ref)
+    with ppsolve.Solver(nx, ny, nz, h, mode=mode, tol=1e-12) as S:
+        S.set_density(rho_t)
+        p_t, st = S.solve(rhs_t)
+    p = c(p_t)
+    exact = sigma * kappa * (a - a.mean())
+    err = P.relative_linf_error(p, exact)
+    bx, by, bz = P.face_coefficients(rho)
+    fx, fy, fz = P.surface_force(a, kappa, sigma, h)
+    gx, gy, gz = P.gradient(p, h)
+    spurious = max(np.max(np.abs(bx * (fx - gx))), np.max(np.abs(by * (fy - gy))), np.max(np.abs(bz * (fz - gz))))
+    scale = np.max(np.abs(bz * fz))
+    print(f"   pressure jump error {err:.2e}; spurious face velocity / force scale {spurious / scale:.2e}", flush=True)
+    assert err < 1e-9
+    assert spurious < 1e-9 * scale
+    assert cref.relative_residual(rho, rhs_ref, p, h) <= 1e-12

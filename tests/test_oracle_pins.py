@@ -381,3 +381,38 @@ def test_generator_union_and_wrap():
     inside = ((X - cen[0, 0]) ** 2 + (Y - cen[0, 1]) ** 2 + dz ** 2) < 2.5 ** 2
     brute = inside.reshape(8, 4, 12, 4, 12, 4).sum(axis=(1, 3, 5)) / 64.0
     np.testing.assert_array_equal(fast, brute)
+
+
+# ------------------------------------------------------------------ projection and surface tension
+
+def test_projection_leaves_divergence_equal_to_residual():
+    case = W.random_small_case(12, 6, 5, 8)
+    h, dt = case.h, 0.25
+    rho = P.density_from_fraction(case.alpha)
+    b = P.divergence(case.u, case.v, case.w, h, dt)
+    p = P.solve_dense(rho, b, h)
+    un, vn, wn = P.project(rho, p, case.u, case.v, case.w, h, dt)
+    d = P.divergence(un, vn, wn, h)
+    np.testing.assert_allclose(d, dt * (b - b.mean() - P.apply_operator(rho, p, h)) + dt * b.mean(), atol=1e-9)
+    assert np.max(np.abs(d - d.mean())) < 1e-9 * np.max(np.abs(b))
+
+
+def test_static_bubble_exact_curvature_balances_to_machine_zero():
+    """Section 2.1: with exact curvature the surface-tension pressure cancels the
+    interface force exactly.  For constant kappa the discrete solution is
+    p~ = sigma kappa (a - mean a), and the face velocity it drives is zero."""
+    nx = 16
+    h = 1.0 / nx
+    a = W.volume_fraction(nx, nx, 16, np.array([[8.3, 7.6, 8.1]]), 7.0)
+    rho = P.density_from_fraction(a)
+    sigma, kappa = 0.072, 2.0 / (3.5 * h)
+    rhs = P.surface_tension_rhs(rho, a, kappa, sigma, h)
+    p = P.solve_dense(rho, rhs, h) if a.size <= 4096 else None
+    exact = sigma * kappa * (a - a.mean())
+    assert P.relative_linf_error(p, exact) < 1e-9
+    bx, by, bz = P.face_coefficients(rho)
+    fx, fy, fz = P.surface_force(a, kappa, sigma, h)
+    gx, gy, gz = P.gradient(p, h)
+    spurious = max(np.max(np.abs(bx * (fx - gx))), np.max(np.abs(by * (fy - gy))), np.max(np.abs(bz * (fz - gz))))
+    scale = np.max(np.abs(bx * fx))
+    assert spurious < 1e-9 * scale
