@@ -60,8 +60,14 @@ typedef struct {
     int max_iters;     /* PCG iterations (refined mode: total inner iterations); <= 0 selects 1000 */
     int pre_sweeps;    /* red-black Gauss-Seidel sweeps on the finest level; <= 0 selects 1 */
     int post_sweeps;   /* sweeps on coarse levels; <= 0 selects 2 */
-    int flags;         /* reserved, pass 0 */
+    int flags;         /* PP_FLAG_* bits, 0 for the default solver */
+    double omega;      /* SOR factor of the red-black smoother, in [0, 2); <= 0 selects 1 (Gauss-Seidel) */
 } pp_config;
+
+/* flags: run multigrid cycles as the solver, x += M (bbar - A x), instead of
+ * using them to precondition conjugate gradients -- the "multigrid accelerated
+ * red black SOR" form of Section 2.1.  Float64 mode only. */
+#define PP_FLAG_MG_SOLVER 1
 
 typedef struct {
     int iters;              /* PCG iterations (refined mode: outer refinement steps) */

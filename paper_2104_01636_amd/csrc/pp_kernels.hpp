@@ -182,18 +182,19 @@ __device__ inline size_t cell(int nx, int ny, int i, int j, int k)
 // Red-black Gauss-Seidel from a zero guess: red cells (i+j+k even) get f/D,
 // black cells one update from their red neighbours (computed on the fly).
 template <class T, bool FINE>
-__global__ void __launch_bounds__(kBlock) k_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper)
+__global__ void __launch_bounds__(kBlock) k_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
+                                                        T omega)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     if (!t.act) return;
     for (int k = t.k0; k < t.k1; ++k) {
         size_t c = cell(L.nx, L.ny, t.i, t.j, k);
         if (((t.i + t.j + k) & 1) == 0) {
-            x[c] = f[c] * L.invd[c];
+            x[c] = omega * (f[c] * L.invd[c]);
         } else {
             T s, d;
-            nbsum<T, FINE>(L, t.i, t.j, k, c, [&](size_t m, int, int, int) { return f[m] * L.invd[m]; }, s, d);
-            x[c] = (s + f[c]) * L.invd[c];
+            nbsum<T, FINE>(L, t.i, t.j, k, c, [&](size_t m, int, int, int) { return omega * (f[m] * L.invd[m]); }, s, d);
+            x[c] = omega * ((s + f[c]) * L.invd[c]);
         }
     }
 }
@@ -202,7 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_first(LevelView<T> L, const T
 // launch also reduces sum(x) and <x, q> over all cells after the update.
 template <class T, bool FINE, int NDOT>
 __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
-                                                       const T* __restrict__ q, Reduce R)
+                                                       const T* __restrict__ q, Reduce R, T omega)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     double acc[NDOT > 0 ? NDOT : 1] = {};
@@ -214,6 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T*
                 T s, d;
                 nbsum<T, FINE>(L, t.i, t.j, k, c, [&](size_t m, int, int, int) { return x[m]; }, s, d);
                 xv = (s + f[c]) * L.invd[c];
+                if (omega != T(1)) xv = x[c] + omega * (xv - x[c]);
                 x[c] = xv;
             } else {
                 xv = x[c];
@@ -254,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_restrict(LevelView<T> L, co
 // sees the corrected red values.
 template <class T, bool FINE>
 __global__ void __launch_bounds__(kBlock) k_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
-                                                         const T* __restrict__ e, T wc, T* __restrict__ y, int kper)
+                                                         const T* __restrict__ e, T wc, T* __restrict__ y, int kper, T omega)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     if (!t.act) return;
@@ -267,7 +269,12 @@ __global__ void __launch_bounds__(kBlock) k_prolong_black(LevelView<T> L, const 
         } else {
             T s, d;
             nbsum<T, FINE>(L, t.i, t.j, k, c, xe, s, d);
-            y[c] = (s + f[c]) * L.invd[c];
+            T gs = (s + f[c]) * L.invd[c];
+            if (omega != T(1)) {
+                T xo = x[c] + wc * e[cell(cnx, cny, t.i >> 1, t.j >> 1, k >> 1)];
+                gs = xo + omega * (gs - xo);
+            }
+            y[c] = gs;
         }
     }
 }

@@ -88,7 +88,7 @@ enum : int {
     G_BASE = 200,
     G_BSUM = G_BASE + 0, G_BBAD = G_BASE + 1, G_FN2 = G_BASE + 2, G_TRR = G_BASE + 3, G_TRSUM = G_BASE + 4,
     G_XSUM = G_BASE + 5, G_XBAD = G_BASE + 6, G_SCALE = G_BASE + 7, G_INVSCALE = G_BASE + 8, G_RHOSUM = G_BASE + 9,
-    G_RHOBAD = G_BASE + 10,
+    G_RHOBAD = G_BASE + 10, G_ONE = G_BASE + 11,
     kSlots = 256
 };
 static inline int lslot(int l, int s) { return l * kLevSlots + s; }
@@ -139,6 +139,8 @@ struct Params {
     double wc = 2.0;
     double inner_floor = 1e-5;  // refined mode: inner float32 relative tolerance floor
     bool graphs = true;
+    double omega = 1.0;         // SOR factor of the red-black smoother
+    bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
     int max_outer = 40;
 };
 
@@ -300,6 +302,9 @@ static bool valid_cfg(const pp_config* cfg, std::string* why)
     if (!(cfg->h > 0.0) || !std::isfinite(cfg->h)) { if (why) *why = "h must be > 0"; return false; }
     if (!(cfg->tol > 0.0) || !std::isfinite(cfg->tol)) { if (why) *why = "tol must be > 0"; return false; }
     if (cfg->mode != PP_FP64 && cfg->mode != PP_FP32_REFINED) { if (why) *why = "unknown mode"; return false; }
+    if (cfg->omega < 0.0 || cfg->omega >= 2.0 || !std::isfinite(cfg->omega)) { if (why) *why = "omega must be in [0, 2)"; return false; }
+    if ((cfg->flags & PP_FLAG_MG_SOLVER) && cfg->mode != PP_FP64) { if (why) *why = "the multigrid-solver form is float64 only"; return false; }
+    if (cfg->flags & ~PP_FLAG_MG_SOLVER) { if (why) *why = "unknown flag bits"; return false; }
     if ((size_t)cfg->nx * cfg->ny * cfg->nz > (size_t)1 << 31) { if (why) *why = "grid too large"; return false; }
     {
         Geo g = geo(cfg->nx, cfg->ny, cfg->nz);
@@ -492,13 +497,13 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
     TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
                  (double)V.n * sz * (ndot >= 2 ? 5.5 : 4.5));
     if (fine) {
-        if (ndot == 0) k_smooth_half<T, true, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
-        else if (ndot == 1) k_smooth_half<T, true, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
-        else k_smooth_half<T, true, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+        if (ndot == 0) k_smooth_half<T, true, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else if (ndot == 1) k_smooth_half<T, true, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else k_smooth_half<T, true, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
     } else {
-        if (ndot == 0) k_smooth_half<T, false, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
-        else if (ndot == 1) k_smooth_half<T, false, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
-        else k_smooth_half<T, false, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R);
+        if (ndot == 0) k_smooth_half<T, false, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else if (ndot == 1) k_smooth_half<T, false, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else k_smooth_half<T, false, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
     }
     check_launch();
 }
@@ -525,8 +530,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const T* 
             Geo g = geo(V.nx, V.ny, V.nz);
             {
                 TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 4.0);
-                if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
-                else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
+                if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
+                else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
             }
             check_launch();
             const int ns = H->prm.coarse_sweeps;
@@ -545,8 +550,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const T* 
     Geo g = geo(V.nx, V.ny, V.nz);
     {
         TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 4.0);
-        if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
-        else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper);
+        if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
+        else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
     }
     check_launch();
     for (int s = 1; s < nu; ++s) {
@@ -572,8 +577,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const T* 
     }
     {
         TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (5.0 + 0.125));
-        if (fine) k_prolong_black<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper);
-        else k_prolong_black<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper);
+        if (fine) k_prolong_black<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper, (T)H->prm.omega);
+        else k_prolong_black<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper, (T)H->prm.omega);
     }
     check_launch();
     T* cur = V.c2;
@@ -827,6 +832,29 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
     if (fn == 0.0) {
         PP_HIP(hipMemsetAsync(p, 0, sizeof(double) * (size_t)cfg.nx * cfg.ny * cfg.nz, H->stream));
         PP_HIP(hipStreamSynchronize(H->stream));
+    } else if (cfg.mode == PP_FP64 && H->prm.mg_solver) {
+        // the paper's form: multigrid cycles with red-black SOR as the solver, x += M (f - K x)
+        Hier<double>& Hh = H->h64;
+        const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
+        Lev<double>& V = Hh.L[0];
+        PP_HIP(hipMemcpyAsync(Hh.x, p, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+        converged = false;
+        for (;;) {
+            double rn = true_residual(H, Hh.x);
+            rel = rn / fn;
+            if (rel <= cfg.tol) { converged = true; break; }
+            if (!(rel == rel)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
+            if (iters >= max_it) break;
+            double* z = mgcycle(H, Hh, 0, V.rhs, 0, (const double*)nullptr);
+            k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, Hh.x, z, V.rhs, V.q, coef(H, G_ONE, -1, 1.0),
+                                                                        0, 1, 0, red(H, G_FN2));
+            check_launch();
+            ++iters;
+        }
+        remove_mean(H, Hh.x);
+        rel = true_residual(H, Hh.x) / fn;
+        converged = converged || rel <= cfg.tol;
+        PP_HIP(hipMemcpyAsync(p, Hh.x, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
     } else if (cfg.mode == PP_FP64) {
         Hier<double>& Hh = H->h64;
         const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
@@ -887,6 +915,11 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
 {
     if (cfg && cfg->pre_sweeps > 0) p.nu0 = cfg->pre_sweeps;
     if (cfg && cfg->post_sweeps > 0) p.nuc = cfg->post_sweeps;
+    if (cfg && cfg->omega > 0.0) p.omega = cfg->omega;
+    if (cfg && (cfg->flags & PP_FLAG_MG_SOLVER)) {
+        p.mg_solver = true;
+        p.kmax = 0;  // plain V-cycles: no Krylov steps anywhere in this form
+    }
     if (const char* s = getenv("PP_KMAX")) p.kmax = atoi(s);
     if (const char* s = getenv("PP_KIT")) p.kit = std::max(1, atoi(s));
     if (const char* s = getenv("PP_WC")) p.wc = atof(s);
@@ -968,6 +1001,10 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
         PP_HIP(hipEventCreate(&H->ev1));
         PP_HIP(hipMemsetAsync(H->counter, 0, 64 * sizeof(unsigned), H->stream));
         PP_HIP(hipMemsetAsync(H->slots, 0, kSlots * sizeof(double), H->stream));
+        {
+            double one = 1.0;
+            write_slots(H, G_ONE, &one, 1);
+        }
         PP_HIP(hipStreamSynchronize(H->stream));
         return PP_OK;
     });

@@ -42,7 +42,8 @@ class PPError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("h", ctypes.c_double),
                 ("mode", ctypes.c_int), ("tol", ctypes.c_double), ("max_iters", ctypes.c_int),
-                ("pre_sweeps", ctypes.c_int), ("post_sweeps", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("pre_sweeps", ctypes.c_int), ("post_sweeps", ctypes.c_int), ("flags", ctypes.c_int),
+                ("omega", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -100,9 +101,14 @@ def _check(rc: int, handle=None):
         raise PPError(rc, msg)
 
 
-def make_config(nx, ny, nz, h=None, mode="fp64", tol=1e-10, max_iters=1000, pre_sweeps=0, post_sweeps=0):
+PP_FLAG_MG_SOLVER = 1
+
+
+def make_config(nx, ny, nz, h=None, mode="fp64", tol=1e-10, max_iters=1000, pre_sweeps=0, post_sweeps=0, flags=0,
+                omega=0.0):
     return Config(int(nx), int(ny), int(nz), float(h if h is not None else 1.0 / nx), MODES[mode] if isinstance(mode, str)
-                  else int(mode), float(tol), int(max_iters), int(pre_sweeps), int(post_sweeps), 0)
+                  else int(mode), float(tol), int(max_iters), int(pre_sweeps), int(post_sweeps), int(flags),
+                  float(omega))
 
 
 def footprint_bytes(nx, ny, nz, mode="fp64", **kw) -> int:
