@@ -924,6 +924,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_KIT")) p.kit = std::max(1, atoi(s));
     if (const char* s = getenv("PP_WC")) p.wc = atof(s);
     if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
+    if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_INNER_TOL")) p.inner_floor = atof(s);
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
 }
