@@ -31,6 +31,47 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+def serving_leg(args, dev, log):
+    """Serving workload: independent duct cases of mixed sizes arriving as a Poisson
+    stream, solved (refined form, 1e-8) by the library's request loop."""
+    import ctypes
+
+    import torch
+    from paper_2104_01636_amd import ppsolve, serve, workload as W
+
+    t0 = time.time()
+    reqs = W.serving_requests(args.serving_requests, rate_hz=args.serving_rate, seed=4)
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    items, keep = [], []
+    for r in reqs:
+        nx, ny, nz = r["grid"]
+        c = W.make_case(nx, ny, nz, r["n_bubbles"], r["diameter"], seed=r["seed"])
+        rho_t = ppsolve.density_from_fraction(g(c.alpha))
+        rhs_t = ppsolve.divergence(g(c.u), g(c.v), g(c.w), c.h)
+        out_t = torch.empty_like(rhs_t)
+        keep.append((rho_t, rhs_t, out_t))
+        items.append(dict(arrival_s=r["arrival_s"], case_id=r["index"],
+                          cfg=ppsolve.make_config(nx, ny, nz, c.h, "fp32_refined", 1e-8, 4000),
+                          rho=ctypes.c_void_p(rho_t.data_ptr()), rhs=ctypes.c_void_p(rhs_t.data_ptr()),
+                          p_out=ctypes.c_void_p(out_t.data_ptr())))
+    torch.cuda.synchronize()
+    log(f"serving: {len(items)} requests generated in {time.time() - t0:.1f}s")
+    with serve.Server(int(args.serving_budget_gb * (1 << 30)), slots=args.serving_slots) as srv:
+        res = serve.replay(srv, items)
+        st = srv.stats()
+    bad = [r for r in res if r["status"] != 0]
+    iters = [r["stats"]["inner_iters_total"] for r in res if r["status"] == 0]
+    out = {"requests": len(items), "rate_per_s": args.serving_rate, "slots": args.serving_slots,
+           "budget_gb": args.serving_budget_gb, "tol": 1e-8, "form": "fp32_refined",
+           "latency_p50_ms": round(st["latency_p50_ms"], 3), "latency_p99_ms": round(st["latency_p99_ms"], 3),
+           "latency_max_ms": round(st["latency_max_ms"], 3), "solves_per_s": round(st["solves_per_s"], 2),
+           "max_concurrent": st["max_running"], "evictions": st["evictions"],
+           "peak_resident_gb": round(st["peak_resident_bytes"] / (1 << 30), 3), "failed": len(bad),
+           "inner_iters_median": int(np.median(iters)) if iters else None}
+    log(f"serving: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +84,11 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware traffic counters)")
     ap.add_argument("--forms", default="fp32_refined,fp64")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving leg (Poisson arrivals, mixed grids); 0 skips it")
+    ap.add_argument("--serving-rate", type=float, default=40.0)
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-budget-gb", type=float, default=24.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the solve is not sharded across GPUs); use --gpus 1",
@@ -143,6 +189,10 @@ def main():
     else:
         kern_tab = {}
 
+    serving = None
+    if args.serving_requests > 0:
+        serving = serving_leg(args, dev, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         # CPU baseline: the float64 oracle on the same input, a bounded number of iterations
@@ -186,6 +236,7 @@ def main():
         "cells_per_s_solved": round(n / (ms_per_step * 1e-3), 1),
         "roofline": roof,
         "kernels": kern_tab,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
