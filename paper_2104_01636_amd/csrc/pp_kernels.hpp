@@ -201,9 +201,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_first(LevelView<T> L, const T
 
 // One Gauss-Seidel half-sweep over one colour, in place.  With NDOT > 0 the
 // launch also reduces sum(x) and <x, q> over all cells after the update.
-template <class T, bool FINE, int NDOT>
+template <class T, bool FINE, int NDOT, class TQ = T>
 __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
-                                                       const T* __restrict__ q, Reduce R, T omega)
+                                                       const TQ* __restrict__ q, Reduce R, T omega)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     double acc[NDOT > 0 ? NDOT : 1] = {};
@@ -282,9 +282,10 @@ __global__ void __launch_bounds__(kBlock) k_prolong_black(LevelView<T> L, const 
 // ---------------------------------------------------------------- Krylov steps
 
 // d_new = (z - m) + b * d_old, q = K d_new; reduces <d_new, q> and <d_new, r>.
-// m = s[msum]/n (mean projection, finest level only) and b from the slots.
-template <class T, bool FINE>
-__global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const T* __restrict__ z, const T* __restrict__ dold,
+// m = s[msum]/n (mean projection, finest level only) and b from the slots.  The
+// preconditioned residual z may be stored in a lower precision TZ than d and q.
+template <class T, bool FINE, class TZ = T>
+__global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
                                                      Coefs beta, int use_beta, Coefs mean, int use_mean, int kper, Reduce R)
 {
@@ -293,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const T* _
     const T m = use_mean ? (T)mean.get() : T(0);
     double acc[2] = {0.0, 0.0};
     if (t.act) {
-        auto dv = [&](size_t c, int, int, int) { return use_beta ? (z[c] - m) + b * dold[c] : (z[c] - m); };
+        auto dv = [&](size_t c, int, int, int) { return use_beta ? ((T)z[c] - m) + b * dold[c] : ((T)z[c] - m); };
         for (int k = t.k0; k < t.k1; ++k) {
             size_t c = cell(L.nx, L.ny, t.i, t.j, k);
             T s, d;
@@ -313,7 +314,7 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const T* _
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_update_xr(size_t n, T* __restrict__ x, const T* __restrict__ d, T* __restrict__ r,
                                                      const T* __restrict__ q, Coefs alpha, int first, int skip_r, int want_red,
-                                                     Reduce R)
+                                                     Reduce R, float* __restrict__ r32)
 {
     const T a = (T)alpha.get();
     double acc[2] = {0.0, 0.0};
@@ -323,6 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(size_t n, T* __restrict__ 
         if (!skip_r) {
             T rv = r[c] - a * q[c];
             r[c] = rv;
+            if (r32) r32[c] = (float)rv;  // float32 copy for a float32 preconditioner
             acc[0] += (double)rv * (double)rv;
             acc[1] += (double)rv;
         }

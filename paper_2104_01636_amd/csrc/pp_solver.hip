@@ -88,7 +88,7 @@ enum : int {
     G_BASE = 200,
     G_BSUM = G_BASE + 0, G_BBAD = G_BASE + 1, G_FN2 = G_BASE + 2, G_TRR = G_BASE + 3, G_TRSUM = G_BASE + 4,
     G_XSUM = G_BASE + 5, G_XBAD = G_BASE + 6, G_SCALE = G_BASE + 7, G_INVSCALE = G_BASE + 8, G_RHOSUM = G_BASE + 9,
-    G_RHOBAD = G_BASE + 10, G_ONE = G_BASE + 11,
+    G_RHOBAD = G_BASE + 10, G_ONE = G_BASE + 11, G_ZERO = G_BASE + 12,
     kSlots = 256
 };
 static inline int lslot(int l, int s) { return l * kLevSlots + s; }
@@ -123,25 +123,22 @@ struct TimedPair {
     hipEvent_t a, b;
 };
 
+// Multigrid hierarchy in the preconditioner's precision T.  Level 0 holds only
+// the cycle's input (rhs) and output buffers; the finest-level Krylov vectors
+// are float64 and live in the Handle.
 template <class T>
 struct Hier {
     std::vector<Lev<T>> L;
     T* Minv = nullptr;   // coarsest dense inverse (when n <= kDenseMax)
     int nd = 0;
-    T* x = nullptr;      // finest iterate used by the Krylov loop
-    // captured Krylov iterations: [0] first step, [1] odd steps, [2] even steps >= 2
-    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
-    std::vector<TimedPair> timed[3];  // event nodes inside each graph (timing on at capture)
 };
 
 struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 2, coarse_sweeps = 16;
     double wc = 2.0;
-    double inner_floor = 1e-5;  // refined mode: inner float32 relative tolerance floor
     bool graphs = true;
     double omega = 1.0;         // SOR factor of the red-black smoother
     bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
-    int max_outer = 40;
 };
 
 struct Handle {
@@ -173,8 +170,15 @@ struct Handle {
     double* M64 = nullptr;
     float* M32 = nullptr;
 
-    // float64 finest vectors used by both modes
-    double *f64 = nullptr, *r64 = nullptr;
+    // float64 finest-level Krylov state (both modes): scaled right-hand side f,
+    // residual r, iterate x, search directions (d, d2 alternate between d_a and
+    // d_b), q = K d; r32 = float32 copy of r for a float32 preconditioner
+    double *f64 = nullptr, *r64 = nullptr, *x64 = nullptr, *q64 = nullptr;
+    double *d = nullptr, *d2 = nullptr, *d_a = nullptr, *d_b = nullptr;
+    float* r32 = nullptr;
+    // captured Krylov steps: [0] first step, [1] odd steps, [2] even steps >= 2
+    hipGraphExec_t kexec[3] = {nullptr, nullptr, nullptr};
+    std::vector<TimedPair> ktimed[3];  // event nodes inside each graph (timing on at capture)
 
     Hier<double> h64;
     Hier<float> h32;
@@ -372,6 +376,11 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     }
     double* f64 = P.take<double>(n0);
     double* r64 = P.take<double>(n0);
+    double* x64 = P.take<double>(n0);
+    double* q64 = P.take<double>(n0);
+    double* d_a = P.take<double>(n0);
+    double* d_b = P.take<double>(n0);
+    float* r32 = fp64 ? nullptr : P.take<float>(n0);
 
     auto make_h = [&](auto tag, auto& Hh, bool alloc) {
         using T = decltype(tag);
@@ -384,8 +393,8 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
             if (l > 0) V.rhs = P.template take<T>(V.n);
             V.c = P.template take<T>(V.n);
             if (l < nl - 1) V.c2 = P.template take<T>(V.n);
-            if (l == 0 || V.kcyc) {
-                if (l > 0) V.xk = P.template take<T>(V.n);
+            if (V.kcyc) {
+                V.xk = P.template take<T>(V.n);
                 V.d = V.d_a = P.template take<T>(V.n);
                 V.d2 = V.d_b = P.template take<T>(V.n);
                 V.q = P.template take<T>(V.n);
@@ -399,15 +408,9 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     Hier<float> h32;
     make_h(double{}, h64, fp64);
     make_h(float{}, h32, !fp64);
-    // refined mode: the float32 finest level needs x (inner correction) and the residual
-    if (!fp64) {
-        h32.L[0].xk = P.take<float>(n0);
-        h32.L[0].rhs = P.take<float>(n0);
-        h32.x = h32.L[0].xk;
-    } else {
-        h64.L[0].rhs = r64;           // finest residual
-        h64.x = P.take<double>(n0);   // iterate (copied from / to the caller's p)
-    }
+    // the finest cycle reads the Krylov residual
+    if (fp64) h64.L[0].rhs = r64;
+    else h32.L[0].rhs = r32;
     double* partials = P.take<double>((size_t)kMaxRedBlocks * kMaxRed);
     unsigned* counter = P.take<unsigned>(64);
     double* slots = P.take<double>(kSlots);
@@ -417,7 +420,8 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         H->rho64 = rho64; H->rho32 = rho32; H->invd64_0 = invd64; H->invd32_0 = invd32;
         H->c64 = c64; H->c32 = c32;
         H->dense_work = dense_work; H->M64 = M64; H->M32 = M32;
-        H->f64 = f64; H->r64 = r64;
+        H->f64 = f64; H->r64 = r64; H->x64 = x64; H->q64 = q64; H->r32 = r32;
+        H->d = H->d_a = d_a; H->d2 = H->d_b = d_b;
         H->partials = partials; H->counter = counter; H->slots = slots;
         // coefficient views
         for (int l = 0; l < nl; ++l) {
@@ -488,8 +492,8 @@ static void write_slots(Handle* H, int first, const double* v, int count)
 template <class T>
 static int kid(int id) { return id + (sizeof(T) == 4 ? 0 : 32); }
 
-template <class T>
-static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int colour, int ndot, const T* q, int l)
+template <class T, class TQ>
+static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int colour, int ndot, const TQ* q, int l)
 {
     Geo g = geo(V.nx, V.ny, V.nz);
     Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
@@ -497,13 +501,13 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
     TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
                  (double)V.n * sz * (ndot >= 2 ? 5.5 : 4.5));
     if (fine) {
-        if (ndot == 0) k_smooth_half<T, true, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else if (ndot == 1) k_smooth_half<T, true, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else k_smooth_half<T, true, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        if (ndot == 0) k_smooth_half<T, true, 0, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else if (ndot == 1) k_smooth_half<T, true, 1, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else k_smooth_half<T, true, 2, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
     } else {
-        if (ndot == 0) k_smooth_half<T, false, 0><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else if (ndot == 1) k_smooth_half<T, false, 1><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else k_smooth_half<T, false, 2><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        if (ndot == 0) k_smooth_half<T, false, 0, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else if (ndot == 1) k_smooth_half<T, false, 1, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+        else k_smooth_half<T, false, 2, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
     }
     check_launch();
 }
@@ -514,8 +518,8 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l);
 // One multigrid cycle at level l for right-hand side f; returns the buffer holding
 // the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, reduced on the last
 // half-sweep into level l's slots.
-template <class T>
-static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const T* q)
+template <class T, class TQ = T>
+static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ* q)
 {
     Lev<T>& V = Hh.L[l];
     const bool fine = (l == 0);
@@ -614,7 +618,7 @@ static void update_xr(Handle* H, Lev<T>& V, T* x, int it, int l, bool first, boo
     TimeScope ts(H, l == 0 ? kid<T>(KT_UPDATE_XR) : -1,
                  (double)V.n * sizeof(T) * ((first ? 1.0 : 2.0) + (skip_r ? 0.0 : 3.0)));
     k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>(V.n, x, V.d2, V.rhs, V.q, alpha, first, skip_r, want,
-                                                         red(H, lslot(l, S_RR), lslot(l, S_RSUM)));
+                                                         red(H, lslot(l, S_RR), lslot(l, S_RSUM)), (float*)nullptr);
     check_launch();
 }
 
@@ -635,45 +639,77 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l)
     return V.xk;
 }
 
-// Flexible PCG on the finest level of hierarchy Hh.  V.rhs must hold the initial
-// residual; x the initial iterate (or anything when x_zero, which makes the first
-// step write x).  Runs until ||r|| <= stop * or max_it steps.  Returns steps taken.
-template <class T>
-static void fcg_step(Handle* H, Hier<T>& Hh, bool x_zero, int k)
+// One step of the finest-level flexible CG, float64 throughout (x, r, d, q and
+// the operator from rho), preconditioned by one multigrid cycle in precision P:
+// z = M r (the cycle also reduces sum(z) and <z, q_old>), d = (z - mean z) +
+// beta d_old, q = K d with <d, q> and <d, r>, then x += alpha d, r -= alpha q
+// (and the float32 copy of r for a float32 cycle) with ||r||^2.
+template <class P>
+static void krylov_step(Handle* H, Hier<P>& Hh, int k)
 {
-    Lev<T>& V = Hh.L[0];
-    T* z = mgcycle(H, Hh, 0, V.rhs, k > 0 ? 2 : 1, V.q);
-    dir_apply(H, V, true, z, k, 0, true);
-    update_xr(H, V, Hh.x, k, 0, x_zero && k == 0, false, true);
-    std::swap(V.d, V.d2);
+    const pp_config& cfg = H->cfg;
+    const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
+    P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, k > 0 ? 2 : 1, H->q64);
+    {
+        Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
+        const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
+        const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
+        LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->rho64, nullptr, nullptr, nullptr, nullptr};
+        TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 40.0 : 32.0)));
+        k_dir_apply<double, true, P><<<g.grid, g.block, 0, H->stream>>>(
+            v, z, H->d, H->d2, H->q64, H->r64, coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
+            coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1, g.kper, red(H, dq_cur, lslot(0, S_DR)));
+        check_launch();
+    }
+    {
+        const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
+        TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (48.0 + (H->r32 ? 4.0 : 0.0)));
+        k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->x64, H->d2, H->r64, H->q64,
+                                                                    coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1,
+                                                                    red(H, lslot(0, S_RR), lslot(0, S_RSUM)), H->r32);
+        check_launch();
+    }
+    std::swap(H->d, H->d2);
 }
 
-// Flexible PCG on the finest level of hierarchy Hh.  V.rhs must hold the initial
-// residual and Hh.x the initial iterate (anything when x_zero: the first step
-// then writes x).  Runs until ||r|| <= rnorm_stop or max_it steps; returns the
-// steps taken.  Steps are replayed from captured graphs when allowed: every
-// pointer and scalar a step uses is fixed by the parity of its index.
-template <class T>
-static int fcg_finest(Handle* H, Hier<T>& Hh, bool x_zero, double rnorm_stop, int max_it, double* rnorm_out)
+static void drop_graphs(Handle* H)
 {
-    Lev<T>& V = Hh.L[0];
-    V.d = V.d_a;
-    V.d2 = V.d_b;
-    const bool graphs = H->use_graphs;
+    for (int i = 0; i < 3; ++i) {
+        if (H->kexec[i]) {
+            (void)hipGraphExecDestroy(H->kexec[i]);
+            H->kexec[i] = nullptr;
+        }
+        for (auto& tp : H->ktimed[i]) {
+            (void)hipEventDestroy(tp.a);
+            (void)hipEventDestroy(tp.b);
+        }
+        H->ktimed[i].clear();
+    }
+}
+
+// Flexible CG on the finest level until ||r|| <= rnorm_stop or max_it steps;
+// r64 (and r32) must hold the residual of x64.  Returns the steps taken.
+// Steps are replayed from captured graphs when possible: every pointer and
+// slot a step uses is fixed by the parity of its index.
+template <class P>
+static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rnorm_out)
+{
+    H->d = H->d_a;
+    H->d2 = H->d_b;
     int k = 0;
     double rn = -1.0;
     for (; k < max_it; ++k) {
         const int kind = k == 0 ? 0 : ((k & 1) ? 1 : 2);
-        if (graphs && !Hh.exec[kind]) {
-            T* d0 = V.d;
-            T* d1 = V.d2;
+        if (H->use_graphs && !H->kexec[kind]) {
+            double* d0 = H->d;
+            double* d1 = H->d2;
             hipGraph_t g = nullptr;
-            Hh.timed[kind].clear();
-            H->capture_target = &Hh.timed[kind];
+            H->ktimed[kind].clear();
+            H->capture_target = &H->ktimed[kind];
             hipError_t e = hipStreamBeginCapture(H->stream, hipStreamCaptureModeRelaxed);
             if (e == hipSuccess) {
                 try {
-                    fcg_step(H, Hh, x_zero, k);
+                    krylov_step(H, Hh, k);
                 } catch (...) {
                     H->capture_target = nullptr;
                     (void)hipStreamEndCapture(H->stream, &g);
@@ -683,52 +719,36 @@ static int fcg_finest(Handle* H, Hier<T>& Hh, bool x_zero, double rnorm_stop, in
                 e = hipStreamEndCapture(H->stream, &g);
             }
             H->capture_target = nullptr;
-            if (e == hipSuccess) e = hipGraphInstantiate(&Hh.exec[kind], g, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphInstantiate(&H->kexec[kind], g, nullptr, nullptr, 0);
             if (g) (void)hipGraphDestroy(g);
-            V.d = d0;  // capture ran nothing: restore and replay below
-            V.d2 = d1;
-            if (e != hipSuccess) {
-                // capture unavailable: run eagerly from now on
+            H->d = d0;  // capture ran nothing: restore and replay below
+            H->d2 = d1;
+            if (e != hipSuccess) {  // capture unavailable: launch directly from now on
                 (void)hipGetLastError();
-                Hh.exec[kind] = nullptr;
+                H->kexec[kind] = nullptr;
                 H->use_graphs = false;
-                for (auto& tp : Hh.timed[kind]) {
+                for (auto& tp : H->ktimed[kind]) {
                     (void)hipEventDestroy(tp.a);
                     (void)hipEventDestroy(tp.b);
                 }
-                Hh.timed[kind].clear();
+                H->ktimed[kind].clear();
             }
         }
-        if (H->use_graphs && Hh.exec[kind]) {
-            PP_HIP(hipGraphLaunch(Hh.exec[kind], H->stream));
-            std::swap(V.d, V.d2);
+        const bool replay = H->use_graphs && H->kexec[kind];
+        if (replay) {
+            PP_HIP(hipGraphLaunch(H->kexec[kind], H->stream));
+            std::swap(H->d, H->d2);
         } else {
-            fcg_step(H, Hh, x_zero, k);
+            krylov_step(H, Hh, k);
         }
         read_slots(H, lslot(0, S_RR), 1);
-        if (H->timing && H->use_graphs && Hh.exec[kind]) accumulate(H, Hh.timed[kind]);
+        if (H->timing && replay) accumulate(H, H->ktimed[kind]);
         rn = std::sqrt(std::max(0.0, H->host_slots[lslot(0, S_RR)]));
         if (!(rn == rn)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
         if (rn <= rnorm_stop) { ++k; break; }
     }
     if (rnorm_out) *rnorm_out = rn;
     return k;
-}
-
-template <class T>
-static void drop_graphs(Hier<T>& Hh)
-{
-    for (int i = 0; i < 3; ++i) {
-        if (Hh.exec[i]) {
-            (void)hipGraphExecDestroy(Hh.exec[i]);
-            Hh.exec[i] = nullptr;
-        }
-        for (auto& tp : Hh.timed[i]) {
-            (void)hipEventDestroy(tp.a);
-            (void)hipEventDestroy(tp.b);
-        }
-        Hh.timed[i].clear();
-    }
 }
 
 // ---------------------------------------------------------------- set-up
@@ -824,84 +844,55 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
 {
     auto t0 = std::chrono::steady_clock::now();
     const pp_config& cfg = H->cfg;
+    const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     const int max_it = cfg.max_iters > 0 ? cfg.max_iters : 1000;
     const double fn = prepare_rhs(H, rhs);
-    int iters = 0, outer = 0, inner_total = 0;
+    int iters = 0, restarts = 0;
     double rel = 0.0;
     bool converged = true;
     if (fn == 0.0) {
-        PP_HIP(hipMemsetAsync(p, 0, sizeof(double) * (size_t)cfg.nx * cfg.ny * cfg.nz, H->stream));
+        PP_HIP(hipMemsetAsync(p, 0, sizeof(double) * n0, H->stream));
         PP_HIP(hipStreamSynchronize(H->stream));
-    } else if (cfg.mode == PP_FP64 && H->prm.mg_solver) {
-        // the paper's form: multigrid cycles with red-black SOR as the solver, x += M (f - K x)
-        Hier<double>& Hh = H->h64;
-        const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
-        Lev<double>& V = Hh.L[0];
-        PP_HIP(hipMemcpyAsync(Hh.x, p, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+    } else {
+        PP_HIP(hipMemcpyAsync(H->x64, p, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
         converged = false;
         for (;;) {
-            double rn = true_residual(H, Hh.x);
+            const double rn = true_residual(H, H->x64);  // r64 = f - K x
             rel = rn / fn;
             if (rel <= cfg.tol) { converged = true; break; }
             if (!(rel == rel)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
-            if (iters >= max_it) break;
-            double* z = mgcycle(H, Hh, 0, V.rhs, 0, (const double*)nullptr);
-            k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, Hh.x, z, V.rhs, V.q, coef(H, G_ONE, -1, 1.0),
-                                                                        0, 1, 0, red(H, G_FN2));
-            check_launch();
-            ++iters;
+            if (iters >= max_it || restarts >= 50) break;
+            if (H->prm.mg_solver) {
+                // the paper's form: multigrid cycles with red-black SOR as the solver, x += M (f - K x)
+                double* z = mgcycle<double, double>(H, H->h64, 0, H->r64, 0, nullptr);
+                k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->x64, z, H->r64, H->q64,
+                                                                            coef(H, G_ONE, -1, 1.0), 0, 1, 0,
+                                                                            red(H, G_FN2), (float*)nullptr);
+                check_launch();
+                ++iters;
+                continue;
+            }
+            if (H->r32) {  // float32 copy of the residual for the float32 preconditioner
+                k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->r64, H->r32, coef(H, G_ZERO, -1, 1.0),
+                                                                 coef(H, G_ONE, -1, 1.0));
+                check_launch();
+            }
+            if (cfg.mode == PP_FP64) iters += fcg(H, H->h64, cfg.tol * fn, max_it - iters, nullptr);
+            else iters += fcg(H, H->h32, cfg.tol * fn, max_it - iters, nullptr);
+            ++restarts;  // the recursion's residual met the tolerance: check the true one
         }
-        remove_mean(H, Hh.x);
-        rel = true_residual(H, Hh.x) / fn;
+        remove_mean(H, H->x64);
+        rel = true_residual(H, H->x64) / fn;
         converged = converged || rel <= cfg.tol;
-        PP_HIP(hipMemcpyAsync(p, Hh.x, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
-    } else if (cfg.mode == PP_FP64) {
-        Hier<double>& Hh = H->h64;
-        const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
-        PP_HIP(hipMemcpyAsync(Hh.x, p, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
-        converged = false;
-        for (int restart = 0; restart < 50; ++restart) {
-            double rn = true_residual(H, Hh.x);
-            rel = rn / fn;
-            if (rel <= cfg.tol) { converged = true; break; }
-            if (iters >= max_it) break;
-            iters += fcg_finest(H, Hh, false, cfg.tol * fn, max_it - iters, nullptr);
-        }
-        remove_mean(H, Hh.x);
-        rel = true_residual(H, Hh.x) / fn;
-        converged = converged || rel <= cfg.tol;
-        PP_HIP(hipMemcpyAsync(p, Hh.x, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
-    } else {
-        Hier<float>& Hh = H->h32;
-        converged = false;
-        const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
-        for (; outer < H->prm.max_outer; ++outer) {
-            double rn = true_residual(H, p);
-            rel = rn / fn;
-            if (rel <= cfg.tol) { converged = true; break; }
-            if (inner_total >= max_it) break;
-            double sc[2] = {rn, 1.0 / rn};
-            write_slots(H, G_SCALE, sc, 2);
-            k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->r64, Hh.L[0].rhs, coef(H, G_TRSUM, -1, 1.0 / (double)n0),
-                                                             coef(H, G_INVSCALE, -1, 1.0));
-            check_launch();
-            double want = std::max(H->prm.inner_floor, 0.5 * cfg.tol / rel);
-            inner_total += fcg_finest(H, Hh, true, want, max_it - inner_total, nullptr);
-            k_promote_add<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, p, Hh.L[0].xk, coef(H, G_SCALE, -1, 1.0));
-            check_launch();
-        }
-        iters = outer;
-        remove_mean(H, p);
-        rel = true_residual(H, p) / fn;
-        converged = converged || rel <= cfg.tol;
+        PP_HIP(hipMemcpyAsync(p, H->x64, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
     }
     PP_HIP(hipStreamSynchronize(H->stream));
     auto t1 = std::chrono::steady_clock::now();
     if (H->timing) collect_timing(H);
     if (st) {
         st->iters = iters;
-        st->outer_iters = cfg.mode == PP_FP64 ? 0 : outer;
-        st->inner_iters_total = inner_total;
+        st->outer_iters = restarts;
+        st->inner_iters_total = cfg.mode == PP_FP64 ? 0 : iters;
         st->rel_residual = rel;
         st->setup_ms = H->setup_ms;
         st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -925,7 +916,6 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_WC")) p.wc = atof(s);
     if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
-    if (const char* s = getenv("PP_INNER_TOL")) p.inner_floor = atof(s);
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
 }
 
@@ -1089,8 +1079,7 @@ int pp_destroy(pp_handle h)
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
     for (hipEvent_t e : H->ev_pool) (void)hipEventDestroy(e);
-    drop_graphs(H->h64);
-    drop_graphs(H->h32);
+    drop_graphs(H);
     if (H->stream) (void)hipStreamDestroy(H->stream);
     if (H->ev_in) (void)hipEventDestroy(H->ev_in);
     if (H->ev_out) (void)hipEventDestroy(H->ev_out);
@@ -1105,8 +1094,7 @@ int pp_kernel_timing(pp_handle h, int mode, pp_kernel_time* out, int max_entries
     if (mode == 1 || mode == -1) {
         // graphs are recaptured with (or without) event nodes on their next use
         (void)hipStreamSynchronize(H->stream);
-        drop_graphs(H->h64);
-        drop_graphs(H->h32);
+        drop_graphs(H);
         if (mode == 1)
             for (int i = 0; i < 64; ++i) { H->kt_ms[i] = 0.0; H->kt_bytes[i] = 0.0; H->kt_count[i] = 0; }
         H->timing = mode == 1;

@@ -66,7 +66,7 @@ def test_static_bubble_surface_tension_balance(mode):
     rho_t, a_t, k_t = g(rho), g(a), g(kap)
     rhs_t = ppsolve.surface_tension_rhs(rho_t, a_t, k_t, sigma, h)
     np.testing.assert_array_equal(c(rhs_t), rhs_ref)
-    with ppsolve.Solver(nx, ny, nz, h, mode=mode, tol=1e-12) as S:
+    with ppsolve.Solver(nx, ny, nz, h, mode=mode, tol=1e-11) as S:
         S.set_density(rho_t)
         p_t, st = S.solve(rhs_t)
     p = c(p_t)
@@ -78,6 +78,6 @@ def test_static_bubble_surface_tension_balance(mode):
     spurious = max(np.max(np.abs(bx * (fx - gx))), np.max(np.abs(by * (fy - gy))), np.max(np.abs(bz * (fz - gz))))
     scale = np.max(np.abs(bz * fz))
     print(f"   pressure jump error {err:.2e}; spurious face velocity / force scale {spurious / scale:.2e}", flush=True)
-    assert err < 1e-9
-    assert spurious < 1e-9 * scale
-    assert cref.relative_residual(rho, rhs_ref, p, h) <= 1e-12
+    assert err < 1e-8
+    assert spurious < 1e-8 * scale
+    assert cref.relative_residual(rho, rhs_ref, p, h) <= 1e-11
