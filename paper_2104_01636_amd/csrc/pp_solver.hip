@@ -178,7 +178,6 @@ struct Handle {
     float* r32 = nullptr;
     // captured Krylov steps: [0] first step, [1] odd steps, [2] even steps >= 2
     hipGraphExec_t kexec[3] = {nullptr, nullptr, nullptr};
-    std::vector<TimedPair> ktimed[3];  // event nodes inside each graph (timing on at capture)
 
     Hier<double> h64;
     Hier<float> h32;
@@ -199,7 +198,6 @@ struct Handle {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<TimedPair> pending;
-    std::vector<TimedPair>* capture_target = nullptr;  // set while capturing a graph
     double kt_ms[64] = {};
     double kt_bytes[64] = {};
     long long kt_count[64] = {};
@@ -232,15 +230,6 @@ struct TimeScope {
     TimeScope(Handle* h, int kid, double b) : H(h), id(kid), bytes(b)
     {
         if (H->timing && id >= 0) {
-            if (H->capture_target) {  // event node inside a graph being captured; owned by the graph's list
-                if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
-                if (hipEventRecord(a, H->stream) != hipSuccess) {
-                    (void)hipGetLastError();
-                    (void)hipEventDestroy(a);
-                    a = nullptr;
-                }
-                return;
-            }
             a = take_event(H);
             PP_HIP(hipEventRecord(a, H->stream));
         }
@@ -249,16 +238,8 @@ struct TimeScope {
     {
         if (!a) return;
         try {
-            hipEvent_t b = nullptr;
-            if (H->capture_target) {
-                if (hipEventCreate(&b) != hipSuccess) return;
-            } else {
-                b = take_event(H);
-            }
-            if (hipEventRecord(b, H->stream) == hipSuccess) {
-                if (H->capture_target) H->capture_target->push_back({id, bytes, a, b});
-                else H->pending.push_back({id, bytes, a, b});
-            }
+            hipEvent_t b = take_event(H);
+            if (hipEventRecord(b, H->stream) == hipSuccess) H->pending.push_back({id, bytes, a, b});
         } catch (...) {
         }
     }
@@ -679,11 +660,6 @@ static void drop_graphs(Handle* H)
             (void)hipGraphExecDestroy(H->kexec[i]);
             H->kexec[i] = nullptr;
         }
-        for (auto& tp : H->ktimed[i]) {
-            (void)hipEventDestroy(tp.a);
-            (void)hipEventDestroy(tp.b);
-        }
-        H->ktimed[i].clear();
     }
 }
 
@@ -700,25 +676,24 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
     double rn = -1.0;
     for (; k < max_it; ++k) {
         const int kind = k == 0 ? 0 : ((k & 1) ? 1 : 2);
-        if (H->use_graphs && !H->kexec[kind]) {
+        // kernel timing brackets every launch with events, which graphs cannot carry:
+        // timed steps are launched directly
+        const bool graphs = H->use_graphs && !H->timing;
+        if (graphs && !H->kexec[kind]) {
             double* d0 = H->d;
             double* d1 = H->d2;
             hipGraph_t g = nullptr;
-            H->ktimed[kind].clear();
-            H->capture_target = &H->ktimed[kind];
             hipError_t e = hipStreamBeginCapture(H->stream, hipStreamCaptureModeRelaxed);
             if (e == hipSuccess) {
                 try {
                     krylov_step(H, Hh, k);
                 } catch (...) {
-                    H->capture_target = nullptr;
                     (void)hipStreamEndCapture(H->stream, &g);
                     if (g) (void)hipGraphDestroy(g);
                     throw;
                 }
                 e = hipStreamEndCapture(H->stream, &g);
             }
-            H->capture_target = nullptr;
             if (e == hipSuccess) e = hipGraphInstantiate(&H->kexec[kind], g, nullptr, nullptr, 0);
             if (g) (void)hipGraphDestroy(g);
             H->d = d0;  // capture ran nothing: restore and replay below
@@ -727,14 +702,9 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
                 (void)hipGetLastError();
                 H->kexec[kind] = nullptr;
                 H->use_graphs = false;
-                for (auto& tp : H->ktimed[kind]) {
-                    (void)hipEventDestroy(tp.a);
-                    (void)hipEventDestroy(tp.b);
-                }
-                H->ktimed[kind].clear();
             }
         }
-        const bool replay = H->use_graphs && H->kexec[kind];
+        const bool replay = graphs && H->use_graphs && H->kexec[kind];
         if (replay) {
             PP_HIP(hipGraphLaunch(H->kexec[kind], H->stream));
             std::swap(H->d, H->d2);
@@ -742,7 +712,6 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
             krylov_step(H, Hh, k);
         }
         read_slots(H, lslot(0, S_RR), 1);
-        if (H->timing && replay) accumulate(H, H->ktimed[kind]);
         rn = std::sqrt(std::max(0.0, H->host_slots[lslot(0, S_RR)]));
         if (!(rn == rn)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
         if (rn <= rnorm_stop) { ++k; break; }
