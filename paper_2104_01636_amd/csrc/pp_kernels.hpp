@@ -7,14 +7,17 @@
 // after the step list), walls in x and y and periodicity in z (Section 4).
 // Internally every level solves K x = f with the positive semi-definite
 //     (K x)_c = D_c x_c - sum_f W_f x_nb(f),   D_c = sum_f W_f,
-// where on the finest level W_f = beta_f (recomputed from rho on the fly, so a
-// pass reads one density value per cell instead of three face arrays) and on
-// coarse levels W_f is the sum of the four fine faces that form the coarse
-// face (the Galerkin product P^T K P for injection prolongation P).
+// where on the finest level W_f = beta_f (so K = -h^2 A) and on coarse levels
+// W_f is the sum of the four fine faces that form the coarse face (the
+// Galerkin product P^T K P for injection prolongation P).  Face weights are
+// computed once per density and stored: W_x[c] is the +x face of cell c (zero
+// on the wall face i = nx-1), W_y likewise, W_z[c] the +z face (the last plane's
+// face joins plane 0).  The solve kernels therefore do no divisions.
 //
-// Layout: flat index i + nx*(j + ny*k), x fastest.  Kernels run a 2-D tile of
-// threads over (x, y) and march a contiguous range of z planes per block, so
-// the z neighbours of a plane were touched by the same block one step before.
+// Layout: flat index i + nx*(j + ny*k), x fastest; 32-bit indices (a level has
+// fewer than 2^31 cells).  Grid kernels run a 2-D tile of threads over (x, y)
+// and march a contiguous range of z planes per block, so the z neighbours of a
+// plane were touched by the same block one step before.
 //
 // Reductions accumulate in float64 whatever the vector precision: each block
 // reduces with wavefront shuffles and LDS, writes its partial, and the last
@@ -31,12 +34,11 @@ constexpr int kBlock = 256;          // threads per block for grid kernels
 constexpr int kMaxRedBlocks = 2048;  // upper bound on blocks of a reducing launch
 constexpr int kMaxRed = 4;           // values reduced by one launch
 
-// Coefficients of one level, in precision T.
+// Operator of one level, in precision T.
 template <class T>
 struct LevelView {
     int nx, ny, nz;
-    const T* rho;   // finest level: cell densities (coarse levels: nullptr)
-    const T* wx;    // coarse levels: +x face weight of each cell (0 on the wall face)
+    const T* wx;    // +x face weight of each cell (0 on the wall face)
     const T* wy;
     const T* wz;    // +z face weight (the last plane's face joins plane 0)
     const T* invd;  // 1 / D_c
@@ -58,39 +60,23 @@ struct Coefs {
     __device__ inline double get() const { return den < 0 ? sign * s[num] : sign * s[num] / s[den]; }
 };
 
-template <class T>
-__device__ inline T beta2(T a, T b);
-template <>
-__device__ inline double beta2<double>(double a, double b) { return 2.0 / (a + b); }
-template <>
-__device__ inline float beta2<float>(float a, float b) { return 2.0f * __builtin_amdgcn_rcpf(a + b); }
+__device__ inline int cell(int nx, int ny, int i, int j, int k) { return i + nx * (j + ny * k); }
 
 // s = sum_f W_f val(nb(f)), d = sum_f W_f; val(m, i, j, k) gets the neighbour's
 // flat index and coordinates.
-template <class T, bool FINE, class F>
-__device__ inline void nbsum(const LevelView<T>& L, int i, int j, int k, size_t c, F val, T& s, T& d)
+template <class T, class F>
+__device__ inline void nbsum(const LevelView<T>& L, int i, int j, int k, int c, F val, T& s, T& d)
 {
-    const size_t sy = (size_t)L.nx, sz = (size_t)L.nx * L.ny;
-    const size_t cb = k > 0 ? c - sz : c + (size_t)(L.nz - 1) * sz;
-    const size_t ct = k < L.nz - 1 ? c + sz : c - (size_t)(L.nz - 1) * sz;
+    const int sy = L.nx, sz = L.nx * L.ny;
     const int kb = k > 0 ? k - 1 : L.nz - 1, kt = k < L.nz - 1 ? k + 1 : 0;
+    const int cb = c + (kb - k) * sz, ct = c + (kt - k) * sz;
     T ss = T(0), dd = T(0);
-    if constexpr (FINE) {
-        const T rc = L.rho[c];
-        if (i > 0) { T w = beta2<T>(L.rho[c - 1], rc); ss += w * val(c - 1, i - 1, j, k); dd += w; }
-        if (i < L.nx - 1) { T w = beta2<T>(rc, L.rho[c + 1]); ss += w * val(c + 1, i + 1, j, k); dd += w; }
-        if (j > 0) { T w = beta2<T>(L.rho[c - sy], rc); ss += w * val(c - sy, i, j - 1, k); dd += w; }
-        if (j < L.ny - 1) { T w = beta2<T>(rc, L.rho[c + sy]); ss += w * val(c + sy, i, j + 1, k); dd += w; }
-        { T w = beta2<T>(L.rho[cb], rc); ss += w * val(cb, i, j, kb); dd += w; }
-        { T w = beta2<T>(rc, L.rho[ct]); ss += w * val(ct, i, j, kt); dd += w; }
-    } else {
-        if (i > 0) { T w = L.wx[c - 1]; ss += w * val(c - 1, i - 1, j, k); dd += w; }
-        if (i < L.nx - 1) { T w = L.wx[c]; ss += w * val(c + 1, i + 1, j, k); dd += w; }
-        if (j > 0) { T w = L.wy[c - sy]; ss += w * val(c - sy, i, j - 1, k); dd += w; }
-        if (j < L.ny - 1) { T w = L.wy[c]; ss += w * val(c + sy, i, j + 1, k); dd += w; }
-        { T w = L.wz[cb]; ss += w * val(cb, i, j, kb); dd += w; }
-        { T w = L.wz[c]; ss += w * val(ct, i, j, kt); dd += w; }
-    }
+    if (i > 0) { T w = L.wx[c - 1]; ss += w * val(c - 1, i - 1, j, k); dd += w; }
+    if (i < L.nx - 1) { T w = L.wx[c]; ss += w * val(c + 1, i + 1, j, k); dd += w; }
+    if (j > 0) { T w = L.wy[c - sy]; ss += w * val(c - sy, i, j - 1, k); dd += w; }
+    if (j < L.ny - 1) { T w = L.wy[c]; ss += w * val(c + sy, i, j + 1, k); dd += w; }
+    { T w = L.wz[cb]; ss += w * val(cb, i, j, kb); dd += w; }
+    { T w = L.wz[c]; ss += w * val(ct, i, j, kt); dd += w; }
     s = ss;
     d = dd;
 }
@@ -172,36 +158,32 @@ __device__ inline Tile tile(int nx, int ny, int nz, int kper)
     t.act = t.i < nx && t.j < ny;
     return t;
 }
-__device__ inline size_t cell(int nx, int ny, int i, int j, int k)
-{
-    return (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * (size_t)k);
-}
 
 // ---------------------------------------------------------------- smoothing
 
-// Red-black Gauss-Seidel from a zero guess: red cells (i+j+k even) get f/D,
-// black cells one update from their red neighbours (computed on the fly).
-template <class T, bool FINE>
+// Red-black SOR from a zero guess: red cells (i+j+k even) get omega f/D, black
+// cells one update from their red neighbours (computed on the fly).
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
                                                         T omega)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     if (!t.act) return;
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(L.nx, L.ny, t.i, t.j, k);
+        const int c = cell(L.nx, L.ny, t.i, t.j, k);
         if (((t.i + t.j + k) & 1) == 0) {
             x[c] = omega * (f[c] * L.invd[c]);
         } else {
             T s, d;
-            nbsum<T, FINE>(L, t.i, t.j, k, c, [&](size_t m, int, int, int) { return omega * (f[m] * L.invd[m]); }, s, d);
+            nbsum<T>(L, t.i, t.j, k, c, [&](int m, int, int, int) { return omega * (f[m] * L.invd[m]); }, s, d);
             x[c] = omega * ((s + f[c]) * L.invd[c]);
         }
     }
 }
 
-// One Gauss-Seidel half-sweep over one colour, in place.  With NDOT > 0 the
-// launch also reduces sum(x) and <x, q> over all cells after the update.
-template <class T, bool FINE, int NDOT, class TQ = T>
+// One SOR half-sweep over one colour, in place.  With NDOT > 0 the launch also
+// reduces sum(x) (and <x, q> for NDOT = 2) over all cells after the update.
+template <class T, int NDOT, class TQ = T>
 __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
                                                        const TQ* __restrict__ q, Reduce R, T omega)
 {
@@ -209,11 +191,11 @@ __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T*
     double acc[NDOT > 0 ? NDOT : 1] = {};
     if (t.act) {
         for (int k = t.k0; k < t.k1; ++k) {
-            size_t c = cell(L.nx, L.ny, t.i, t.j, k);
+            const int c = cell(L.nx, L.ny, t.i, t.j, k);
             T xv;
             if (((t.i + t.j + k) & 1) == colour) {
                 T s, d;
-                nbsum<T, FINE>(L, t.i, t.j, k, c, [&](size_t m, int, int, int) { return x[m]; }, s, d);
+                nbsum<T>(L, t.i, t.j, k, c, [&](int m, int, int, int) { return x[m]; }, s, d);
                 xv = (s + f[c]) * L.invd[c];
                 if (omega != T(1)) xv = x[c] + omega * (xv - x[c]);
                 x[c] = xv;
@@ -228,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T*
 }
 
 // Restriction of the residual: rhs_c(I,J,K) = sum over the 8 children of (f - K x).
-template <class T, bool FINE>
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                              T* __restrict__ rc, int cnx, int cny, int cnz, int kper)
 {
@@ -236,44 +218,42 @@ __global__ void __launch_bounds__(kBlock) k_residual_restrict(LevelView<T> L, co
     if (!t.act) return;
     for (int K = t.k0; K < t.k1; ++K) {
         T acc = T(0);
-#pragma unroll
+#pragma unroll 1
         for (int dk = 0; dk < 2; ++dk)
 #pragma unroll
             for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
                 for (int di = 0; di < 2; ++di) {
-                    int i = 2 * t.i + di, j = 2 * t.j + dj, k = 2 * K + dk;
-                    size_t c = cell(L.nx, L.ny, i, j, k);
+                    const int i = 2 * t.i + di, j = 2 * t.j + dj, k = 2 * K + dk;
+                    const int c = cell(L.nx, L.ny, i, j, k);
                     T s, d;
-                    nbsum<T, FINE>(L, i, j, k, c, [&](size_t m, int, int, int) { return x[m]; }, s, d);
+                    nbsum<T>(L, i, j, k, c, [&](int m, int, int, int) { return x[m]; }, s, d);
                     acc += f[c] - (d * x[c] - s);
                 }
         rc[cell(cnx, cny, t.i, t.j, K)] = acc;
     }
 }
 
-// Out of place: y = x + wc * P e on red cells, then one black half-sweep that
-// sees the corrected red values.
-template <class T, bool FINE>
+// Out of place: y = x + wc * P e on red cells, then one black SOR half-sweep
+// that sees the corrected red values.
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                          const T* __restrict__ e, T wc, T* __restrict__ y, int kper, T omega)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     if (!t.act) return;
     const int cnx = L.nx >> 1, cny = L.ny >> 1;
-    auto xe = [&](size_t m, int i, int j, int k) { return x[m] + wc * e[cell(cnx, cny, i >> 1, j >> 1, k >> 1)]; };
+    auto xe = [&](int m, int i, int j, int k) { return x[m] + wc * e[cell(cnx, cny, i >> 1, j >> 1, k >> 1)]; };
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(L.nx, L.ny, t.i, t.j, k);
+        const int c = cell(L.nx, L.ny, t.i, t.j, k);
+        const T xo = x[c] + wc * e[cell(cnx, cny, t.i >> 1, t.j >> 1, k >> 1)];
         if (((t.i + t.j + k) & 1) == 0) {
-            y[c] = x[c] + wc * e[cell(cnx, cny, t.i >> 1, t.j >> 1, k >> 1)];
+            y[c] = xo;
         } else {
             T s, d;
-            nbsum<T, FINE>(L, t.i, t.j, k, c, xe, s, d);
+            nbsum<T>(L, t.i, t.j, k, c, xe, s, d);
             T gs = (s + f[c]) * L.invd[c];
-            if (omega != T(1)) {
-                T xo = x[c] + wc * e[cell(cnx, cny, t.i >> 1, t.j >> 1, k >> 1)];
-                gs = xo + omega * (gs - xo);
-            }
+            if (omega != T(1)) gs = xo + omega * (gs - xo);
             y[c] = gs;
         }
     }
@@ -284,7 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_black(LevelView<T> L, const 
 // d_new = (z - m) + b * d_old, q = K d_new; reduces <d_new, q> and <d_new, r>.
 // m = s[msum]/n (mean projection, finest level only) and b from the slots.  The
 // preconditioned residual z may be stored in a lower precision TZ than d and q.
-template <class T, bool FINE, class TZ = T>
+template <class T, class TZ = T>
 __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
                                                      Coefs beta, int use_beta, Coefs mean, int use_mean, int kper, Reduce R)
@@ -294,13 +274,13 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* 
     const T m = use_mean ? (T)mean.get() : T(0);
     double acc[2] = {0.0, 0.0};
     if (t.act) {
-        auto dv = [&](size_t c, int, int, int) { return use_beta ? ((T)z[c] - m) + b * dold[c] : ((T)z[c] - m); };
+        auto dv = [&](int c, int, int, int) { return use_beta ? ((T)z[c] - m) + b * dold[c] : ((T)z[c] - m); };
         for (int k = t.k0; k < t.k1; ++k) {
-            size_t c = cell(L.nx, L.ny, t.i, t.j, k);
+            const int c = cell(L.nx, L.ny, t.i, t.j, k);
             T s, d;
-            nbsum<T, FINE>(L, t.i, t.j, k, c, dv, s, d);
-            T dc = dv(c, 0, 0, 0);
-            T qc = d * dc - s;
+            nbsum<T>(L, t.i, t.j, k, c, dv, s, d);
+            const T dc = dv(c, 0, 0, 0);
+            const T qc = d * dc - s;
             dnew[c] = dc;
             q[c] = qc;
             acc[0] += (double)dc * (double)qc;
@@ -310,21 +290,23 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* 
     reduce_finish<2>(acc, R);
 }
 
-// x += a d (or x = a d when first), r -= a q (unless skip_r); reduces ||r||^2 and sum(r).
+// x += a d (or x = a d when first), r -= a q (unless skip_r); reduces ||r||^2 and
+// sum(r); with r32 also writes the float32 copy of r.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_update_xr(size_t n, T* __restrict__ x, const T* __restrict__ d, T* __restrict__ r,
+__global__ void __launch_bounds__(kBlock) k_update_xr(int n, T* __restrict__ x, const T* __restrict__ d, T* __restrict__ r,
                                                      const T* __restrict__ q, Coefs alpha, int first, int skip_r, int want_red,
                                                      Reduce R, float* __restrict__ r32)
 {
     const T a = (T)alpha.get();
     double acc[2] = {0.0, 0.0};
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+    const int stride = gridDim.x * blockDim.x;
+#pragma unroll 2
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
         x[c] = first ? a * d[c] : x[c] + a * d[c];
         if (!skip_r) {
-            T rv = r[c] - a * q[c];
+            const T rv = r[c] - a * q[c];
             r[c] = rv;
-            if (r32) r32[c] = (float)rv;  // float32 copy for a float32 preconditioner
+            if (r32) r32[c] = (float)rv;
             acc[0] += (double)rv * (double)rv;
             acc[1] += (double)rv;
         }
@@ -338,15 +320,15 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restri
 {
     __shared__ T fs[kBlock];
     for (int r0 = 0; r0 < n; r0 += kBlock) {
-        int r = r0 + threadIdx.x;
+        const int r = r0 + threadIdx.x;
         T acc = T(0);
         for (int c0 = 0; c0 < n; c0 += kBlock) {
             __syncthreads();
             if (c0 + threadIdx.x < n) fs[threadIdx.x] = f[c0 + threadIdx.x];
             __syncthreads();
-            int cm = min(kBlock, n - c0);
+            const int cm = min(kBlock, n - c0);
             if (r < n)
-                for (int c = 0; c < cm; ++c) acc += M[(size_t)(c0 + c) * n + r] * fs[c];
+                for (int c = 0; c < cm; ++c) acc += M[(c0 + c) * n + r] * fs[c];
         }
         if (r < n) x[r] = acc;
     }
@@ -354,35 +336,36 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restri
 
 // ---------------------------------------------------------------- float64 outer pieces
 
-// r = f - K x on the finest level in float64; reduces ||r||^2 and sum(r).
-template <class T, bool FINE>
-__global__ void __launch_bounds__(kBlock) k_true_residual(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
-                                                         T* __restrict__ r, int kper, Reduce R)
+// r = f - K x in float64; reduces ||r||^2 and sum(r).
+__global__ void __launch_bounds__(kBlock) k_true_residual(LevelView<double> L, const double* __restrict__ f,
+                                                         const double* __restrict__ x, double* __restrict__ r, int kper,
+                                                         Reduce R)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     double acc[2] = {0.0, 0.0};
     if (t.act) {
         for (int k = t.k0; k < t.k1; ++k) {
-            size_t c = cell(L.nx, L.ny, t.i, t.j, k);
-            T s, d;
-            nbsum<T, FINE>(L, t.i, t.j, k, c, [&](size_t m, int, int, int) { return x[m]; }, s, d);
-            T rv = f[c] - (d * x[c] - s);
+            const int c = cell(L.nx, L.ny, t.i, t.j, k);
+            double s, d;
+            nbsum<double>(L, t.i, t.j, k, c, [&](int m, int, int, int) { return x[m]; }, s, d);
+            const double rv = f[c] - (d * x[c] - s);
             r[c] = rv;
-            acc[0] += (double)rv * (double)rv;
-            acc[1] += (double)rv;
+            acc[0] += rv * rv;
+            acc[1] += rv;
         }
     }
     reduce_finish<2>(acc, R);
 }
 
-// Reduces sum(x), count of non-finite entries (and of entries <= 0 when check_pos).
-__global__ void __launch_bounds__(kBlock) k_sum_check(size_t n, const double* __restrict__ x, int check_pos, Reduce R)
+// Reduces sum(x) over finite entries and the count of non-finite entries (and
+// of entries <= 0 when check_pos).
+__global__ void __launch_bounds__(kBlock) k_sum_check(int n, const double* __restrict__ x, int check_pos, Reduce R)
 {
     double acc[2] = {0.0, 0.0};
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
-        double v = x[c];
-        bool bad = !(v - v == 0.0) || (check_pos && !(v > 0.0));
+    const int stride = gridDim.x * blockDim.x;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const double v = x[c];
+        const bool bad = !(v - v == 0.0) || (check_pos && !(v > 0.0));
         acc[0] += bad ? 0.0 : v;
         acc[1] += bad ? 1.0 : 0.0;
     }
@@ -390,98 +373,54 @@ __global__ void __launch_bounds__(kBlock) k_sum_check(size_t n, const double* __
 }
 
 // y = a * (x - s[slot]/n) in float64, optionally reducing ||y||^2.
-__global__ void __launch_bounds__(kBlock) k_shift_scale(size_t n, const double* __restrict__ x, double* __restrict__ y, double a,
+__global__ void __launch_bounds__(kBlock) k_shift_scale(int n, const double* __restrict__ x, double* __restrict__ y, double a,
                                                        Coefs mean, int want_red, Reduce R)
 {
     const double m = mean.get();
     double acc[1] = {0.0};
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
-        double v = a * (x[c] - m);
+    const int stride = gridDim.x * blockDim.x;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const double v = a * (x[c] - m);
         y[c] = v;
         acc[0] += v * v;
     }
     if (want_red) reduce_finish<1>(acc, R);
 }
 
-// r32 = (float)((r64 - s[mean]/n) * inv_scale)
-__global__ void __launch_bounds__(kBlock) k_demote(size_t n, const double* __restrict__ r, float* __restrict__ r32, Coefs mean,
-                                                  Coefs inv_scale)
+// r32 = (float) r64
+__global__ void __launch_bounds__(kBlock) k_demote(int n, const double* __restrict__ r, float* __restrict__ r32)
 {
-    const double m = mean.get(), a = inv_scale.get();
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) r32[c] = (float)((r[c] - m) * a);
-}
-
-// x64 += scale * (double)e32
-__global__ void __launch_bounds__(kBlock) k_promote_add(size_t n, double* __restrict__ x, const float* __restrict__ e, Coefs scale)
-{
-    const double a = scale.get();
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) x[c] += a * (double)e[c];
+    const int stride = gridDim.x * blockDim.x;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) r32[c] = (float)r[c];
 }
 
 // ---------------------------------------------------------------- set-up
 
-// Copy the caller's density, make the float32 copy and 1/D of the finest level.
-__global__ void __launch_bounds__(kBlock) k_fine_setup(int nx, int ny, int nz, const double* __restrict__ rho_in,
-                                                      double* __restrict__ rho64, float* __restrict__ rho32,
-                                                      double* __restrict__ invd64, float* __restrict__ invd32, int kper)
+// Finest-level face weights beta_f = 2/(rho_L + rho_R): IEEE division, zero on
+// the wall faces, periodic in z.
+__global__ void __launch_bounds__(kBlock) k_fine_faces(int nx, int ny, int nz, const double* __restrict__ rho,
+                                                      double* __restrict__ wx, double* __restrict__ wy, double* __restrict__ wz,
+                                                      int kper)
 {
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
-    LevelView<double> L{nx, ny, nz, rho_in, nullptr, nullptr, nullptr, nullptr};
+    const int sy = nx, sz = nx * ny;
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(nx, ny, t.i, t.j, k);
-        double s, d;
-        nbsum<double, true>(L, t.i, t.j, k, c, [&](size_t, int, int, int) { return 0.0; }, s, d);
-        double rv = rho_in[c];
-        if (rho64) rho64[c] = rv;
-        if (rho32) rho32[c] = (float)rv;
-        double inv = 1.0 / d;
-        if (invd64) invd64[c] = inv;
-        if (invd32) invd32[c] = (float)inv;
+        const int c = cell(nx, ny, t.i, t.j, k);
+        const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
+        const double rc = rho[c];
+        wx[c] = t.i < nx - 1 ? 2.0 / (rc + rho[c + 1]) : 0.0;
+        wy[c] = t.j < ny - 1 ? 2.0 / (rc + rho[c + sy]) : 0.0;
+        wz[c] = 2.0 / (rc + rho[ct]);
     }
 }
 
-// First coarse level from the density: each coarse face weight is the sum of
-// the four fine beta_f that form it.
-__global__ void __launch_bounds__(kBlock) k_coarsen_from_rho(int nx, int ny, int nz, const double* __restrict__ rho, int cnx, int cny,
-                                                            int cnz, double* __restrict__ wx, double* __restrict__ wy,
-                                                            double* __restrict__ wz, int kper)
-{
-    Tile t = tile(cnx, cny, cnz, kper);
-    if (!t.act) return;
-    for (int K = t.k0; K < t.k1; ++K) {
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                if (t.i < cnx - 1) {
-                    int i = 2 * t.i + 1, j = 2 * t.j + a, k = 2 * K + b;
-                    sx += 2.0 / (rho[cell(nx, ny, i, j, k)] + rho[cell(nx, ny, i + 1, j, k)]);
-                }
-                if (t.j < cny - 1) {
-                    int i = 2 * t.i + a, j = 2 * t.j + 1, k = 2 * K + b;
-                    sy += 2.0 / (rho[cell(nx, ny, i, j, k)] + rho[cell(nx, ny, i, j + 1, k)]);
-                }
-                {
-                    int i = 2 * t.i + a, j = 2 * t.j + b, k = 2 * K + 1;
-                    int kp = (k + 1 == nz) ? 0 : k + 1;
-                    sz += 2.0 / (rho[cell(nx, ny, i, j, k)] + rho[cell(nx, ny, i, j, kp)]);
-                }
-            }
-        size_t cc = cell(cnx, cny, t.i, t.j, K);
-        wx[cc] = sx;
-        wy[cc] = sy;
-        wz[cc] = sz;
-    }
-}
-
-// Next coarse level from face weights.
-__global__ void __launch_bounds__(kBlock) k_coarsen_from_w(int nx, int ny, int nz, const double* __restrict__ fx,
-                                                          const double* __restrict__ fy, const double* __restrict__ fz, int cnx,
-                                                          int cny, int cnz, double* __restrict__ wx, double* __restrict__ wy,
-                                                          double* __restrict__ wz, int kper)
+// Next coarse level: each coarse face weight is the sum of the four fine face
+// weights that form it.
+__global__ void __launch_bounds__(kBlock) k_coarsen(int nx, int ny, int nz, const double* __restrict__ fx,
+                                                   const double* __restrict__ fy, const double* __restrict__ fz, int cnx, int cny,
+                                                   int cnz, double* __restrict__ wx, double* __restrict__ wy,
+                                                   double* __restrict__ wz, int kper)
 {
     Tile t = tile(cnx, cny, cnz, kper);
     if (!t.act) return;
@@ -493,28 +432,28 @@ __global__ void __launch_bounds__(kBlock) k_coarsen_from_w(int nx, int ny, int n
                 sy += fy[cell(nx, ny, 2 * t.i + a, 2 * t.j + 1, 2 * K + b)];
                 sz += fz[cell(nx, ny, 2 * t.i + a, 2 * t.j + b, 2 * K + 1)];
             }
-        size_t cc = cell(cnx, cny, t.i, t.j, K);
+        const int cc = cell(cnx, cny, t.i, t.j, K);
         wx[cc] = sx;
         wy[cc] = sy;
         wz[cc] = sz;
     }
 }
 
-// 1/D for a coarse level plus float32 copies of its weights.
-__global__ void __launch_bounds__(kBlock) k_coarse_finish(int nx, int ny, int nz, const double* __restrict__ wx,
-                                                         const double* __restrict__ wy, const double* __restrict__ wz,
-                                                         double* __restrict__ invd64, float* __restrict__ wx32,
-                                                         float* __restrict__ wy32, float* __restrict__ wz32,
-                                                         float* __restrict__ invd32, int kper)
+// 1/D of a level plus float32 copies of its weights (when the float32 arrays exist).
+__global__ void __launch_bounds__(kBlock) k_level_finish(int nx, int ny, int nz, const double* __restrict__ wx,
+                                                        const double* __restrict__ wy, const double* __restrict__ wz,
+                                                        double* __restrict__ invd64, float* __restrict__ wx32,
+                                                        float* __restrict__ wy32, float* __restrict__ wz32,
+                                                        float* __restrict__ invd32, int kper)
 {
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
-    LevelView<double> L{nx, ny, nz, nullptr, wx, wy, wz, nullptr};
+    LevelView<double> L{nx, ny, nz, wx, wy, wz, nullptr};
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(nx, ny, t.i, t.j, k);
+        const int c = cell(nx, ny, t.i, t.j, k);
         double s, d;
-        nbsum<double, false>(L, t.i, t.j, k, c, [&](size_t, int, int, int) { return 0.0; }, s, d);
-        double inv = 1.0 / d;
+        nbsum<double>(L, t.i, t.j, k, c, [&](int, int, int, int) { return 0.0; }, s, d);
+        const double inv = 1.0 / d;
         if (invd64) invd64[c] = inv;
         if (wx32) {
             wx32[c] = (float)wx[c];
@@ -536,28 +475,27 @@ __global__ void __launch_bounds__(kBlock) k_dense_inverse(int nx, int ny, int nz
     const int n = nx * ny * nz;
     const int w2 = 2 * n;
     __shared__ double dmean;
-    LevelView<double> L{nx, ny, nz, nullptr, wx, wy, wz, nullptr};
-    // assemble [K + c 1 1^T | I]
+    LevelView<double> L{nx, ny, nz, wx, wy, wz, nullptr};
     for (int idx = threadIdx.x; idx < n * w2; idx += blockDim.x) work[idx] = 0.0;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int c = 0; c < n; ++c) {
-            int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+            const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
             double ss, d;
-            nbsum<double, false>(L, i, j, k, (size_t)c, [&](size_t, int, int, int) { return 0.0; }, ss, d);
+            nbsum<double>(L, i, j, k, c, [&](int, int, int, int) { return 0.0; }, ss, d);
             s += d;
         }
         dmean = s / n;
     }
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-        double* row = work + (size_t)c * w2;
+        const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        double* row = work + c * w2;
         for (int m = 0; m < n; ++m) row[m] = dmean / n;
-        const size_t sy = nx, sz = (size_t)nx * ny;
-        const int cb = k > 0 ? c - (int)sz : c + (nz - 1) * (int)sz;
-        const int ct = k < nz - 1 ? c + (int)sz : c - (nz - 1) * (int)sz;
+        const int sy = nx, sz = nx * ny;
+        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz;
+        const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
         double d = 0.0;
         if (i > 0) { row[c - 1] -= wx[c - 1]; d += wx[c - 1]; }
         if (i < nx - 1) { row[c + 1] -= wx[c]; d += wx[c]; }
@@ -570,23 +508,23 @@ __global__ void __launch_bounds__(kBlock) k_dense_inverse(int nx, int ny, int nz
     }
     __syncthreads();
     for (int p = 0; p < n; ++p) {
-        double piv = work[(size_t)p * w2 + p];
+        const double piv = work[p * w2 + p];
         __syncthreads();
-        for (int m = threadIdx.x; m < w2; m += blockDim.x) work[(size_t)p * w2 + m] /= piv;
+        for (int m = threadIdx.x; m < w2; m += blockDim.x) work[p * w2 + m] /= piv;
         __syncthreads();
         for (int idx = threadIdx.x; idx < n * w2; idx += blockDim.x) {
-            int r = idx / w2, m = idx % w2;
+            const int r = idx / w2, m = idx % w2;
             if (r == p || m == p) continue;
-            work[idx] -= work[(size_t)r * w2 + p] * work[(size_t)p * w2 + m];
+            work[idx] -= work[r * w2 + p] * work[p * w2 + m];
         }
         __syncthreads();
         for (int r = threadIdx.x; r < n; r += blockDim.x)
-            if (r != p) work[(size_t)r * w2 + p] = 0.0;
+            if (r != p) work[r * w2 + p] = 0.0;
         __syncthreads();
     }
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        int r = idx / n, m = idx % n;
-        double v = work[(size_t)r * w2 + n + m];
+        const int r = idx / n, m = idx % n;
+        const double v = work[r * w2 + n + m];
         M64[idx] = v;
         M32[idx] = (float)v;
     }
@@ -601,7 +539,7 @@ __global__ void __launch_bounds__(kBlock) k_density(size_t n, const double* __re
 #pragma clang fp contract(off)
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
-        double av = a[c];
+        const double av = a[c];
         rho[c] = rho_l * (1.0 - av) + rho_g * av;
     }
 }
@@ -614,30 +552,30 @@ __global__ void __launch_bounds__(kBlock) k_divergence(int nx, int ny, int nz, d
 #pragma clang fp contract(off)
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
-    const size_t sy = nx, sz = (size_t)nx * ny;
+    const int sy = nx, sz = nx * ny;
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(nx, ny, t.i, t.j, k);
-        size_t cb = k > 0 ? c - sz : c + (size_t)(nz - 1) * sz;
-        double ue = t.i < nx - 1 ? u[c] : 0.0;
-        double uw = t.i > 0 ? u[c - 1] : 0.0;
-        double vn = t.j < ny - 1 ? v[c] : 0.0;
-        double vs = t.j > 0 ? v[c - sy] : 0.0;
+        const int c = cell(nx, ny, t.i, t.j, k);
+        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz;
+        const double ue = t.i < nx - 1 ? u[c] : 0.0;
+        const double uw = t.i > 0 ? u[c - 1] : 0.0;
+        const double vn = t.j < ny - 1 ? v[c] : 0.0;
+        const double vs = t.j > 0 ? v[c - sy] : 0.0;
         out[c] = (((ue - uw) + (vn - vs)) + (w[c] - w[cb])) / hd;
     }
 }
 
-// out = A x = div(beta grad x) in float64 (the operator of step 11).
-__global__ void __launch_bounds__(kBlock) k_apply_a(int nx, int ny, int nz, double inv_h2, const double* __restrict__ rho,
-                                                   const double* __restrict__ x, double* __restrict__ out, int kper)
+// out = A x = div(beta grad x) in float64 (the operator of step 11) from the
+// stored finest-level face coefficients.
+__global__ void __launch_bounds__(kBlock) k_apply_a(LevelView<double> L, double inv_h2, const double* __restrict__ x,
+                                                   double* __restrict__ out, int kper)
 {
-    Tile t = tile(nx, ny, nz, kper);
+    Tile t = tile(L.nx, L.ny, L.nz, kper);
     if (!t.act) return;
-    LevelView<double> L{nx, ny, nz, rho, nullptr, nullptr, nullptr, nullptr};
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(nx, ny, t.i, t.j, k);
+        const int c = cell(L.nx, L.ny, t.i, t.j, k);
         const double xc = x[c];
         double s, d;
-        nbsum<double, true>(L, t.i, t.j, k, c, [&](size_t m, int, int, int) { return x[m] - xc; }, s, d);
+        nbsum<double>(L, t.i, t.j, k, c, [&](int m, int, int, int) { return x[m] - xc; }, s, d);
         out[c] = s * inv_h2;
     }
 }
@@ -650,10 +588,10 @@ __global__ void __launch_bounds__(kBlock) k_project(int nx, int ny, int nz, doub
 #pragma clang fp contract(off)
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
-    const size_t sy = nx, sz = (size_t)nx * ny;
+    const int sy = nx, sz = nx * ny;
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(nx, ny, t.i, t.j, k);
-        size_t ct = k < nz - 1 ? c + sz : c - (size_t)(nz - 1) * sz;
+        const int c = cell(nx, ny, t.i, t.j, k);
+        const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
         const double rc = rho[c], pc = p[c];
         u[c] = t.i < nx - 1 ? u[c] - dt * ((2.0 / (rc + rho[c + 1])) * ((p[c + 1] - pc) / h)) : 0.0;
         v[c] = t.j < ny - 1 ? v[c] - dt * ((2.0 / (rc + rho[c + sy])) * ((p[c + sy] - pc) / h)) : 0.0;
@@ -663,8 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_project(int nx, int ny, int nz, doub
 
 // Right-hand side of the surface-tension pressure equation: out = div(beta f)
 // with the face force f = sigma * (kappa_L + kappa_R)/2 * (a_R - a_L)/h.
-__device__ inline double st_flux(const double* rho, const double* a, const double* kap, double sigma, double h, size_t L,
-                                 size_t R)
+__device__ inline double st_flux(const double* rho, const double* a, const double* kap, double sigma, double h, int L, int R)
 {
 #pragma clang fp contract(off)
     const double beta = 2.0 / (rho[L] + rho[R]);
@@ -679,17 +616,17 @@ __global__ void __launch_bounds__(kBlock) k_surface_rhs(int nx, int ny, int nz, 
 #pragma clang fp contract(off)
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
-    const size_t sy = nx, sz = (size_t)nx * ny;
+    const int sy = nx, sz = nx * ny;
     for (int k = t.k0; k < t.k1; ++k) {
-        size_t c = cell(nx, ny, t.i, t.j, k);
-        size_t ct = k < nz - 1 ? c + sz : c - (size_t)(nz - 1) * sz;
-        size_t cb = k > 0 ? c - sz : c + (size_t)(nz - 1) * sz;
-        double fe = t.i < nx - 1 ? st_flux(rho, a, kap, sigma, h, c, c + 1) : 0.0;
-        double fw = t.i > 0 ? st_flux(rho, a, kap, sigma, h, c - 1, c) : 0.0;
-        double fn = t.j < ny - 1 ? st_flux(rho, a, kap, sigma, h, c, c + sy) : 0.0;
-        double fs = t.j > 0 ? st_flux(rho, a, kap, sigma, h, c - sy, c) : 0.0;
-        double ft = st_flux(rho, a, kap, sigma, h, c, ct);
-        double fb = st_flux(rho, a, kap, sigma, h, cb, c);
+        const int c = cell(nx, ny, t.i, t.j, k);
+        const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
+        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz;
+        const double fe = t.i < nx - 1 ? st_flux(rho, a, kap, sigma, h, c, c + 1) : 0.0;
+        const double fw = t.i > 0 ? st_flux(rho, a, kap, sigma, h, c - 1, c) : 0.0;
+        const double fn = t.j < ny - 1 ? st_flux(rho, a, kap, sigma, h, c, c + sy) : 0.0;
+        const double fs = t.j > 0 ? st_flux(rho, a, kap, sigma, h, c - sy, c) : 0.0;
+        const double ft = st_flux(rho, a, kap, sigma, h, c, ct);
+        const double fb = st_flux(rho, a, kap, sigma, h, cb, c);
         out[c] = (((fe - fw) + (fn - fs)) + (ft - fb)) / h;
     }
 }

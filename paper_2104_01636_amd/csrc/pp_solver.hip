@@ -159,11 +159,7 @@ struct Handle {
     char* arena = nullptr;
     size_t arena_bytes = 0;
 
-    // fine coefficients
-    double* rho64 = nullptr;
-    float* rho32 = nullptr;
-    double* invd64_0 = nullptr;
-    float* invd32_0 = nullptr;
+    // face weights per level (c64[0] holds beta_f of the finest level)
     std::vector<Level64> c64;
     std::vector<Level32> c32;
     double* dense_work = nullptr;
@@ -328,13 +324,11 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     auto nn = [&](int l) { return (size_t)nx[l] * ny[l] * nz[l]; };
     Params prm = H ? H->prm : Params{};
 
-    double* rho64 = P.take<double>(n0);
-    float* rho32 = fp64 ? nullptr : P.take<float>(n0);
-    double* invd64 = fp64 ? P.take<double>(n0) : nullptr;
-    float* invd32 = fp64 ? nullptr : P.take<float>(n0);
+    // face weights of every level (level 0: beta_f) in float64, and in the
+    // preconditioner's precision when that is float32; 1/D in that precision
     std::vector<Level64> c64(nl);
     std::vector<Level32> c32(nl);
-    for (int l = 1; l < nl; ++l) {
+    for (int l = 0; l < nl; ++l) {
         c64[l].wx = P.take<double>(nn(l));
         c64[l].wy = P.take<double>(nn(l));
         c64[l].wz = P.take<double>(nn(l));
@@ -398,25 +392,15 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
 
     if (H && base) {
         H->lnx = nx; H->lny = ny; H->lnz = nz; H->nlev = nl;
-        H->rho64 = rho64; H->rho32 = rho32; H->invd64_0 = invd64; H->invd32_0 = invd32;
         H->c64 = c64; H->c32 = c32;
         H->dense_work = dense_work; H->M64 = M64; H->M32 = M32;
         H->f64 = f64; H->r64 = r64; H->x64 = x64; H->q64 = q64; H->r32 = r32;
         H->d = H->d_a = d_a; H->d2 = H->d_b = d_b;
         H->partials = partials; H->counter = counter; H->slots = slots;
-        // coefficient views
+        // operator views
         for (int l = 0; l < nl; ++l) {
-            auto& v64 = h64.L[l].v;
-            auto& v32 = h32.L[l].v;
-            v64 = LevelView<double>{nx[l], ny[l], nz[l], nullptr, nullptr, nullptr, nullptr, nullptr};
-            v32 = LevelView<float>{nx[l], ny[l], nz[l], nullptr, nullptr, nullptr, nullptr, nullptr};
-            if (l == 0) {
-                v64.rho = rho64; v64.invd = invd64;
-                v32.rho = rho32; v32.invd = invd32;
-            } else {
-                v64.wx = c64[l].wx; v64.wy = c64[l].wy; v64.wz = c64[l].wz; v64.invd = c64[l].invd;
-                v32.wx = c32[l].wx; v32.wy = c32[l].wy; v32.wz = c32[l].wz; v32.invd = c32[l].invd;
-            }
+            h64.L[l].v = LevelView<double>{nx[l], ny[l], nz[l], c64[l].wx, c64[l].wy, c64[l].wz, c64[l].invd};
+            h32.L[l].v = LevelView<float>{nx[l], ny[l], nz[l], c32[l].wx, c32[l].wy, c32[l].wz, c32[l].invd};
         }
         H->h64 = h64;
         H->h32 = h32;
@@ -478,18 +462,12 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
 {
     Geo g = geo(V.nx, V.ny, V.nz);
     Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
-    const double sz = sizeof(T);
+    // reads x, f, three face arrays and 1/D; writes one colour (and reads q for the dot)
     TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
-                 (double)V.n * sz * (ndot >= 2 ? 5.5 : 4.5));
-    if (fine) {
-        if (ndot == 0) k_smooth_half<T, true, 0, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else if (ndot == 1) k_smooth_half<T, true, 1, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else k_smooth_half<T, true, 2, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-    } else {
-        if (ndot == 0) k_smooth_half<T, false, 0, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else if (ndot == 1) k_smooth_half<T, false, 1, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-        else k_smooth_half<T, false, 2, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-    }
+                 (double)V.n * (6.5 * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
+    if (ndot == 0) k_smooth_half<T, 0, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+    else if (ndot == 1) k_smooth_half<T, 1, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
+    else k_smooth_half<T, 2, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
     check_launch();
 }
 
@@ -514,9 +492,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
             // finest level cannot be coarsened)
             Geo g = geo(V.nx, V.ny, V.nz);
             {
-                TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 4.0);
-                if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
-                else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
+                TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 6.0);
+                k_smooth_first<T><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
             }
             check_launch();
             const int ns = H->prm.coarse_sweeps;
@@ -534,9 +511,9 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     const int nu = fine ? H->prm.nu0 : H->prm.nuc;
     Geo g = geo(V.nx, V.ny, V.nz);
     {
-        TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 4.0);
-        if (fine) k_smooth_first<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
-        else k_smooth_first<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
+        // reads f, three face arrays and 1/D; writes x
+        TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 6.0);
+        k_smooth_first<T><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
     }
     check_launch();
     for (int s = 1; s < nu; ++s) {
@@ -546,9 +523,9 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     Lev<T>& C = Hh.L[l + 1];
     Geo gc = geo(C.nx, C.ny, C.nz);
     {
-        TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (3.0 + 0.125));
-        if (fine) k_residual_restrict<T, true><<<gc.grid, gc.block, 0, H->stream>>>(V.v, f, V.c, C.rhs, C.nx, C.ny, C.nz, gc.kper);
-        else k_residual_restrict<T, false><<<gc.grid, gc.block, 0, H->stream>>>(V.v, f, V.c, C.rhs, C.nx, C.ny, C.nz, gc.kper);
+        // reads x, f and three face arrays; writes the coarse right-hand side
+        TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (5.0 + 0.125));
+        k_residual_restrict<T><<<gc.grid, gc.block, 0, H->stream>>>(V.v, f, V.c, C.rhs, C.nx, C.ny, C.nz, gc.kper);
     }
     check_launch();
     T* e;
@@ -561,9 +538,9 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         wc = (T)H->prm.wc;
     }
     {
-        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (5.0 + 0.125));
-        if (fine) k_prolong_black<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper, (T)H->prm.omega);
-        else k_prolong_black<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper, (T)H->prm.omega);
+        // reads x, f, three face arrays, 1/D and the coarse correction; writes y
+        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (7.0 + 0.125));
+        k_prolong_black<T><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper, (T)H->prm.omega);
     }
     check_launch();
     T* cur = V.c2;
@@ -583,11 +560,7 @@ static void dir_apply(Handle* H, Lev<T>& V, bool fine, const T* z, int it, int l
     Coefs beta = coef(H, lslot(l, S_ZQ), dq_prev, -1.0);
     Coefs mn = coef(H, lslot(l, S_SUMZ), -1, 1.0 / (double)V.n);
     Reduce R = red(H, dq_cur, lslot(l, S_DR));
-    TimeScope ts(H, fine ? kid<T>(KT_DIR_APPLY) : -1, (double)V.n * sizeof(T) * (it > 0 ? 6.0 : 5.0));
-    if (fine)
-        k_dir_apply<T, true><<<g.grid, g.block, 0, H->stream>>>(V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, g.kper, R);
-    else
-        k_dir_apply<T, false><<<g.grid, g.block, 0, H->stream>>>(V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, g.kper, R);
+    k_dir_apply<T><<<g.grid, g.block, 0, H->stream>>>(V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, g.kper, R);
     check_launch();
 }
 
@@ -596,9 +569,7 @@ static void update_xr(Handle* H, Lev<T>& V, T* x, int it, int l, bool first, boo
 {
     const int dq_cur = lslot(l, (it & 1) ? S_DQ1 : S_DQ0);
     Coefs alpha = coef(H, lslot(l, S_DR), dq_cur, 1.0);
-    TimeScope ts(H, l == 0 ? kid<T>(KT_UPDATE_XR) : -1,
-                 (double)V.n * sizeof(T) * ((first ? 1.0 : 2.0) + (skip_r ? 0.0 : 3.0)));
-    k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>(V.n, x, V.d2, V.rhs, V.q, alpha, first, skip_r, want,
+    k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>((int)V.n, x, V.d2, V.rhs, V.q, alpha, first, skip_r, want,
                                                          red(H, lslot(l, S_RR), lslot(l, S_RSUM)), (float*)nullptr);
     check_launch();
 }
@@ -635,9 +606,10 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
         Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
         const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
         const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
-        LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->rho64, nullptr, nullptr, nullptr, nullptr};
-        TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 40.0 : 32.0)));
-        k_dir_apply<double, true, P><<<g.grid, g.block, 0, H->stream>>>(
+        const LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
+        // reads z, d_old, three float64 face arrays and r; writes d and q
+        TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 64.0 : 56.0)));
+        k_dir_apply<double, P><<<g.grid, g.block, 0, H->stream>>>(
             v, z, H->d, H->d2, H->q64, H->r64, coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
             coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1, g.kper, red(H, dq_cur, lslot(0, S_DR)));
         check_launch();
@@ -645,7 +617,7 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
     {
         const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
         TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (48.0 + (H->r32 ? 4.0 : 0.0)));
-        k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->x64, H->d2, H->r64, H->q64,
+        k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
                                                                     coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1,
                                                                     red(H, lslot(0, S_RR), lslot(0, S_RSUM)), H->r32);
         check_launch();
@@ -729,30 +701,25 @@ static void set_density(Handle* H, const double* rho)
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     PP_HIP(hipEventRecord(H->ev0, H->stream));
     // validate: finite and > 0
-    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, rho, 1, red(H, G_RHOSUM, G_RHOBAD));
+    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, 1, red(H, G_RHOSUM, G_RHOBAD));
     check_launch();
     read_slots(H, G_RHOSUM, 2);
     if (H->host_slots[G_RHOBAD] != 0.0)
         throw Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
                                          " entries that are not finite or not > 0");
-    Geo g0 = geo(cfg.nx, cfg.ny, cfg.nz);
-    k_fine_setup<<<g0.grid, g0.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, rho, H->rho64, H->rho32, H->invd64_0,
-                                                      H->invd32_0, g0.kper);
-    check_launch();
-    for (int l = 1; l < nl; ++l) {
+    for (int l = 0; l < nl; ++l) {
         Geo g = geo(H->lnx[l], H->lny[l], H->lnz[l]);
-        if (l == 1)
-            k_coarsen_from_rho<<<g.grid, g.block, 0, H->stream>>>(H->lnx[0], H->lny[0], H->lnz[0], H->rho64, H->lnx[1],
-                                                                  H->lny[1], H->lnz[1], H->c64[1].wx, H->c64[1].wy,
-                                                                  H->c64[1].wz, g.kper);
+        if (l == 0)
+            k_fine_faces<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, rho, H->c64[0].wx, H->c64[0].wy,
+                                                            H->c64[0].wz, g.kper);
         else
-            k_coarsen_from_w<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l - 1], H->lny[l - 1], H->lnz[l - 1], H->c64[l - 1].wx,
-                                                                H->c64[l - 1].wy, H->c64[l - 1].wz, H->lnx[l], H->lny[l],
-                                                                H->lnz[l], H->c64[l].wx, H->c64[l].wy, H->c64[l].wz, g.kper);
+            k_coarsen<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l - 1], H->lny[l - 1], H->lnz[l - 1], H->c64[l - 1].wx,
+                                                         H->c64[l - 1].wy, H->c64[l - 1].wz, H->lnx[l], H->lny[l], H->lnz[l],
+                                                         H->c64[l].wx, H->c64[l].wy, H->c64[l].wz, g.kper);
         check_launch();
-        k_coarse_finish<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx, H->c64[l].wy,
-                                                           H->c64[l].wz, H->c64[l].invd, H->c32[l].wx, H->c32[l].wy,
-                                                           H->c32[l].wz, H->c32[l].invd, g.kper);
+        k_level_finish<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx, H->c64[l].wy,
+                                                          H->c64[l].wz, H->c64[l].invd, H->c32[l].wx, H->c32[l].wy,
+                                                          H->c32[l].wz, H->c32[l].invd, g.kper);
         check_launch();
     }
     if (H->M64) {
@@ -774,12 +741,12 @@ static double prepare_rhs(Handle* H, const double* rhs)
 {
     const pp_config& cfg = H->cfg;
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
-    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, rhs, 0, red(H, G_BSUM, G_BBAD));
+    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, 0, red(H, G_BSUM, G_BBAD));
     check_launch();
     read_slots(H, G_BSUM, 2);
     if (H->host_slots[G_BBAD] != 0.0)
         throw Fail(PP_ERR_NONFINITE, "rhs has " + std::to_string((long long)H->host_slots[G_BBAD]) + " non-finite entries");
-    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, rhs, H->f64, -cfg.h * cfg.h, coef(H, G_BSUM, -1, 1.0 / (double)n0),
+    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, H->f64, -cfg.h * cfg.h, coef(H, G_BSUM, -1, 1.0 / (double)n0),
                                                           1, red(H, G_FN2));
     check_launch();
     read_slots(H, G_FN2, 1);
@@ -791,9 +758,9 @@ static double true_residual(Handle* H, const double* x)
 {
     const pp_config& cfg = H->cfg;
     Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
-    LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->rho64, nullptr, nullptr, nullptr, nullptr};
+    const LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
     TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * 32.0);
-    k_true_residual<double, true><<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, red(H, G_TRR, G_TRSUM));
+    k_true_residual<<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, red(H, G_TRR, G_TRSUM));
     check_launch();
     read_slots(H, G_TRR, 2);
     return std::sqrt(std::max(0.0, H->host_slots[G_TRR]));
@@ -802,9 +769,9 @@ static double true_residual(Handle* H, const double* x)
 static void remove_mean(Handle* H, double* x)
 {
     const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
-    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, x, 0, red(H, G_XSUM, G_XBAD));
+    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, 0, red(H, G_XSUM, G_XBAD));
     check_launch();
-    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, x, x, 1.0, coef(H, G_XSUM, -1, 1.0 / (double)n0), 0,
+    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, x, 1.0, coef(H, G_XSUM, -1, 1.0 / (double)n0), 0,
                                                           red(H, G_FN2));
     check_launch();
 }
@@ -834,7 +801,7 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
             if (H->prm.mg_solver) {
                 // the paper's form: multigrid cycles with red-black SOR as the solver, x += M (f - K x)
                 double* z = mgcycle<double, double>(H, H->h64, 0, H->r64, 0, nullptr);
-                k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->x64, z, H->r64, H->q64,
+                k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, z, H->r64, H->q64,
                                                                             coef(H, G_ONE, -1, 1.0), 0, 1, 0,
                                                                             red(H, G_FN2), (float*)nullptr);
                 check_launch();
@@ -842,8 +809,7 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
                 continue;
             }
             if (H->r32) {  // float32 copy of the residual for the float32 preconditioner
-                k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>(n0, H->r64, H->r32, coef(H, G_ZERO, -1, 1.0),
-                                                                 coef(H, G_ONE, -1, 1.0));
+                k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->r64, H->r32);
                 check_launch();
             }
             if (cfg.mode == PP_FP64) iters += fcg(H, H->h64, cfg.tol * fn, max_it - iters, nullptr);
@@ -1028,8 +994,8 @@ int pp_apply(pp_handle h, const double* x, double* y)
         PP_HIP(hipSetDevice(H->device));
         enter(H);
         Geo g = geo(H->cfg.nx, H->cfg.ny, H->cfg.nz);
-        k_apply_a<<<g.grid, g.block, 0, H->stream>>>(H->cfg.nx, H->cfg.ny, H->cfg.nz, 1.0 / (H->cfg.h * H->cfg.h), H->rho64, x,
-                                                     y, g.kper);
+        const LevelView<double> v{H->cfg.nx, H->cfg.ny, H->cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
+        k_apply_a<<<g.grid, g.block, 0, H->stream>>>(v, 1.0 / (H->cfg.h * H->cfg.h), x, y, g.kper);
         check_launch();
         leave(H);
         PP_HIP(hipStreamSynchronize(H->stream));
