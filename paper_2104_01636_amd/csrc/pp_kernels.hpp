@@ -334,6 +334,142 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restri
     }
 }
 
+
+// ---------------------------------------------------------------- small coarse levels in one launch
+
+constexpr int kTailMaxLev = 12;
+constexpr int kTailThreads = 1024;
+constexpr int kTailMaxCells = 8192;  // levels at most this large run inside k_tail_vcycle
+
+template <class T>
+struct TailLevel {
+    LevelView<T> v;
+    T* rhs;  // right-hand side (level 0 of the tail: written by the restriction above)
+    T* c;    // result / work vector
+    int n;
+};
+
+template <class T>
+struct TailDesc {
+    int nlev;
+    TailLevel<T> L[kTailMaxLev];
+    const T* Minv;  // dense inverse of the last level (nd > 0), else symmetric sweeps
+    int nd;
+    T wc, omega;
+    int nu, coarse_sweeps;
+};
+
+template <class T>
+__device__ inline void tail_coords(const LevelView<T>& L, int c, int& i, int& j, int& k)
+{
+    const int pl = L.nx * L.ny;
+    k = c / pl;
+    const int r = c - k * pl;
+    j = r / L.nx;
+    i = r - j * L.nx;
+}
+
+// red-black SOR half-sweep of one colour over a whole level, by the whole block
+template <class T>
+__device__ inline void tail_half(const LevelView<T>& L, const T* f, T* x, int n, int colour, T omega)
+{
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int i, j, k;
+        tail_coords(L, c, i, j, k);
+        if (((i + j + k) & 1) != colour) continue;
+        T s, d;
+        nbsum<T>(L, i, j, k, c, [&](int m, int, int, int) { return x[m]; }, s, d);
+        T xv = (s + f[c]) * L.invd[c];
+        if (omega != T(1)) xv = x[c] + omega * (xv - x[c]);
+        x[c] = xv;
+    }
+    __syncthreads();
+}
+
+// One V-cycle over the levels of D (each small enough for one block), from a
+// zero guess at the top; the result is left in D.L[0].c.  Same smoothing,
+// transfers and coarse solve as the per-level kernels.
+template <class T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_vcycle(TailDesc<T> D)
+{
+    const int last = D.nlev - 1;
+    for (int l = 0; l < last; ++l) {
+        const TailLevel<T>& V = D.L[l];
+        // first sweep from zero: red = omega f/D, black from the red values on the fly
+        for (int c = threadIdx.x; c < V.n; c += blockDim.x) {
+            int i, j, k;
+            tail_coords(V.v, c, i, j, k);
+            if (((i + j + k) & 1) == 0) {
+                V.c[c] = D.omega * (V.rhs[c] * V.v.invd[c]);
+            } else {
+                T s, d;
+                nbsum<T>(V.v, i, j, k, c, [&](int m, int, int, int) { return D.omega * (V.rhs[m] * V.v.invd[m]); }, s, d);
+                V.c[c] = D.omega * ((s + V.rhs[c]) * V.v.invd[c]);
+            }
+        }
+        __syncthreads();
+        for (int s = 1; s < D.nu; ++s) {
+            tail_half(V.v, V.rhs, V.c, V.n, 0, D.omega);
+            tail_half(V.v, V.rhs, V.c, V.n, 1, D.omega);
+        }
+        // residual restricted to the next level (sum of the 8 children)
+        const TailLevel<T>& C = D.L[l + 1];
+        for (int cc = threadIdx.x; cc < C.n; cc += blockDim.x) {
+            int I, J, K;
+            tail_coords(C.v, cc, I, J, K);
+            T acc = T(0);
+            for (int dk = 0; dk < 2; ++dk)
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int di = 0; di < 2; ++di) {
+                        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                        const int c = cell(V.v.nx, V.v.ny, i, j, k);
+                        T s, d;
+                        nbsum<T>(V.v, i, j, k, c, [&](int m, int, int, int) { return V.c[m]; }, s, d);
+                        acc += V.rhs[c] - (d * V.c[c] - s);
+                    }
+            C.rhs[cc] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        const TailLevel<T>& B = D.L[last];
+        if (D.nd > 0) {
+            for (int r = threadIdx.x; r < D.nd; r += blockDim.x) {
+                T acc = T(0);
+                for (int c = 0; c < D.nd; ++c) acc += D.Minv[c * D.nd + r] * B.rhs[c];
+                B.c[r] = acc;
+            }
+            __syncthreads();
+        } else {
+            for (int c = threadIdx.x; c < B.n; c += blockDim.x) B.c[c] = T(0);
+            __syncthreads();
+            for (int s = 0; s < D.coarse_sweeps; ++s) {
+                tail_half(B.v, B.rhs, B.c, B.n, 0, D.omega);
+                tail_half(B.v, B.rhs, B.c, B.n, 1, D.omega);
+            }
+            for (int s = 0; s < D.coarse_sweeps; ++s) {
+                tail_half(B.v, B.rhs, B.c, B.n, 1, D.omega);
+                tail_half(B.v, B.rhs, B.c, B.n, 0, D.omega);
+            }
+        }
+    }
+    for (int l = last - 1; l >= 0; --l) {
+        const TailLevel<T>& V = D.L[l];
+        const TailLevel<T>& C = D.L[l + 1];
+        // prolongation and correction of every cell, then black before red
+        for (int c = threadIdx.x; c < V.n; c += blockDim.x) {
+            int i, j, k;
+            tail_coords(V.v, c, i, j, k);
+            V.c[c] += D.wc * C.c[cell(C.v.nx, C.v.ny, i >> 1, j >> 1, k >> 1)];
+        }
+        __syncthreads();
+        for (int s = 0; s < D.nu; ++s) {
+            tail_half(V.v, V.rhs, V.c, V.n, 1, D.omega);
+            tail_half(V.v, V.rhs, V.c, V.n, 0, D.omega);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- float64 outer pieces
 
 // r = f - K x in float64; reduces ||r||^2 and sum(r).

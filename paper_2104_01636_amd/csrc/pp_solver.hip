@@ -131,10 +131,13 @@ struct Hier {
     std::vector<Lev<T>> L;
     T* Minv = nullptr;   // coarsest dense inverse (when n <= kDenseMax)
     int nd = 0;
+    int tail = -1;       // first level of the single-launch tail V-cycle (-1: none)
+    TailDesc<T> td{};
 };
 
 struct Params {
-    int nu0 = 1, nuc = 2, kmax = 2, kit = 2, coarse_sweeps = 16;
+    int nu0 = 1, nuc = 2, kmax = 2, kit = 3, coarse_sweeps = 16;
+    bool tail = true;           // run the small coarse V-levels in one launch
     double wc = 2.0;
     bool graphs = true;
     double omega = 1.0;         // SOR factor of the red-black smoother
@@ -402,6 +405,31 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
             h64.L[l].v = LevelView<double>{nx[l], ny[l], nz[l], c64[l].wx, c64[l].wy, c64[l].wz, c64[l].invd};
             h32.L[l].v = LevelView<float>{nx[l], ny[l], nz[l], c32[l].wx, c32[l].wy, c32[l].wz, c32[l].invd};
         }
+        auto make_tail = [&](auto& Hh) {
+            Hh.tail = -1;
+            if (!prm.tail || nl < 2) return;
+            int t = nl - 1;
+            while (t - 1 >= 1 && !Hh.L[t - 1].kcyc && Hh.L[t - 1].n <= (size_t)kTailMaxCells) --t;
+            if (t == nl - 1 || t <= prm.kmax || nl - t > kTailMaxLev) return;  // need at least two levels
+            Hh.tail = t;
+            auto& D = Hh.td;
+            D.nlev = nl - t;
+            for (int l = t; l < nl; ++l) {
+                auto& V = Hh.L[l];
+                D.L[l - t].v = V.v;
+                D.L[l - t].rhs = V.rhs;
+                D.L[l - t].c = V.c;
+                D.L[l - t].n = (int)V.n;
+            }
+            D.Minv = Hh.Minv;
+            D.nd = Hh.nd;
+            D.wc = prm.wc;
+            D.omega = prm.omega;
+            D.nu = prm.nuc;
+            D.coarse_sweeps = prm.coarse_sweeps;
+        };
+        if (fp64) make_tail(h64);
+        else make_tail(h32);
         H->h64 = h64;
         H->h32 = h32;
     }
@@ -483,6 +511,11 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     Lev<T>& V = Hh.L[l];
     const bool fine = (l == 0);
     const int last = (int)Hh.L.size() - 1;
+    if (l == Hh.tail && l > 0) {
+        k_tail_vcycle<T><<<1, kTailThreads, 0, H->stream>>>(Hh.td);
+        check_launch();
+        return V.c;
+    }
     if (l == last) {
         if (l > 0 && Hh.nd > 0) {
             k_dense_apply<T><<<1, kBlock, 0, H->stream>>>(Hh.nd, Hh.Minv, f, V.c);
@@ -852,6 +885,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
+    if (const char* s = getenv("PP_TAIL")) p.tail = atoi(s) != 0;
 }
 
 }  // namespace pp
