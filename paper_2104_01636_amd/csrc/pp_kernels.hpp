@@ -44,10 +44,11 @@ struct LevelView {
     const T* invd;  // 1 / D_c
 };
 
-// Reduction target: per-block partials, a completion counter and the output slots.
+// Reduction target: per-block partials and the output slots.  A reducing
+// launch writes one partial per block; k_reduce_finish, launched after it on
+// the same stream, sums them in a fixed order.
 struct Reduce {
     double* partials;    // [kMaxRedBlocks * kMaxRed]
-    unsigned* counter;   // zero between launches
     double* out;         // scalar slots receiving the totals
     int slot[kMaxRed];   // slot index per reduced value
 };
@@ -90,16 +91,16 @@ __device__ inline double wave_sum(double x)
     return x;
 }
 
-// Block-reduce NV values, publish the partial, and let the last block write the
-// totals in a fixed order.  Every thread of the block must call this.
+// Block-reduce NV values and store the block's partials.  Every thread of the
+// block must call this.  There is no grid-wide completion step in the kernel:
+// an agent-scope fence per block would write back and invalidate the L2 of
+// its XCD, so the totals are formed by k_reduce_finish after the launch.
 template <int NV>
 __device__ inline void reduce_finish(double (&v)[NV], const Reduce& R)
 {
     __shared__ double sh[NV][kBlock / 64];
-    __shared__ int last;
     const int nthr = blockDim.x * blockDim.y * blockDim.z;
     const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-    const int nblk = gridDim.x * gridDim.y * gridDim.z;
     const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     const int nw = (nthr + 63) / 64;
 #pragma unroll
@@ -115,31 +116,26 @@ __device__ inline void reduce_finish(double (&v)[NV], const Reduce& R)
             for (int w = 0; w < nw; ++w) t += sh[m][w];
             R.partials[(size_t)bid * kMaxRed + m] = t;
         }
-        __threadfence();
-        unsigned prev = atomicAdd(R.counter, 1u);
-        last = (prev == (unsigned)(nblk - 1));
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-#pragma unroll
-    for (int m = 0; m < NV; ++m) {
+}
+
+// Totals of a reducing launch of nblk blocks: partials summed thread-strided,
+// then by wavefront and across wavefronts, always in the same order.  One block.
+__global__ void __launch_bounds__(kBlock) k_reduce_finish(Reduce R, int nblk, int nv)
+{
+    __shared__ double sh[kBlock / 64];
+    for (int m = 0; m < nv; ++m) {
         double t = 0.0;
-        for (int b = tid; b < nblk; b += nthr)
-            t += __hip_atomic_load(&R.partials[(size_t)b * kMaxRed + m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int b = threadIdx.x; b < nblk; b += kBlock) t += R.partials[(size_t)b * kMaxRed + m];
         t = wave_sum(t);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
         __syncthreads();
-        if ((tid & 63) == 0) sh[m][tid >> 6] = t;
-        __syncthreads();
-        if (tid == 0) {
+        if (threadIdx.x == 0) {
             double tot = 0.0;
-            for (int w = 0; w < nw; ++w) tot += sh[m][w];
+            for (int w = 0; w < kBlock / 64; ++w) tot += sh[w];
             R.out[R.slot[m]] = tot;
         }
-    }
-    if (tid == 0) {
-        __threadfence();
-        atomicExch(R.counter, 0u);
+        __syncthreads();
     }
 }
 
@@ -291,24 +287,52 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* 
 }
 
 // x += a d (or x = a d when first), r -= a q (unless skip_r); reduces ||r||^2 and
-// sum(r); with r32 also writes the float32 copy of r.
+// sum(r); with r32 also writes the float32 copy of r.  n is even (every level
+// has an even number of planes): a thread handles pairs of cells with 2-wide
+// loads, two pairs per trip.
+template <class T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_update_xr(int n, T* __restrict__ x, const T* __restrict__ d, T* __restrict__ r,
                                                      const T* __restrict__ q, Coefs alpha, int first, int skip_r, int want_red,
                                                      Reduce R, float* __restrict__ r32)
 {
+    using V = typename Vec2<T>::type;
     const T a = (T)alpha.get();
     double acc[2] = {0.0, 0.0};
+    const int np = n >> 1;
     const int stride = gridDim.x * blockDim.x;
+    V* x2 = reinterpret_cast<V*>(x);
+    const V* d2 = reinterpret_cast<const V*>(d);
+    V* r2 = reinterpret_cast<V*>(r);
+    const V* q2 = reinterpret_cast<const V*>(q);
+    float2* s2 = reinterpret_cast<float2*>(r32);
 #pragma unroll 2
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
-        x[c] = first ? a * d[c] : x[c] + a * d[c];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+        const V dv = d2[p];
+        V xv;
+        if (first) {
+            xv.x = a * dv.x;
+            xv.y = a * dv.y;
+        } else {
+            xv = x2[p];
+            xv.x = xv.x + a * dv.x;
+            xv.y = xv.y + a * dv.y;
+        }
+        x2[p] = xv;
         if (!skip_r) {
-            const T rv = r[c] - a * q[c];
-            r[c] = rv;
-            if (r32) r32[c] = (float)rv;
-            acc[0] += (double)rv * (double)rv;
-            acc[1] += (double)rv;
+            V rv = r2[p];
+            const V qv = q2[p];
+            rv.x = rv.x - a * qv.x;
+            rv.y = rv.y - a * qv.y;
+            r2[p] = rv;
+            if (r32) s2[p] = make_float2((float)rv.x, (float)rv.y);
+            acc[0] += (double)rv.x * (double)rv.x;
+            acc[0] += (double)rv.y * (double)rv.y;
+            acc[1] += (double)rv.x;
+            acc[1] += (double)rv.y;
         }
     }
     if (want_red) reduce_finish<2>(acc, R);
@@ -339,14 +363,16 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restri
 
 constexpr int kTailMaxLev = 12;
 constexpr int kTailThreads = 1024;
-constexpr int kTailMaxCells = 8192;  // levels at most this large run inside k_tail_vcycle
+constexpr int kTailMaxCells = 8192;   // levels at most this large run inside k_tail_vcycle
+constexpr int kTailLdsCells = 9400;   // x of every tail level stays in LDS (sum <= 8192 * 8/7)
 
 template <class T>
 struct TailLevel {
     LevelView<T> v;
-    T* rhs;  // right-hand side (level 0 of the tail: written by the restriction above)
-    T* c;    // result / work vector
+    T* rhs;   // right-hand side (level 0 of the tail: written by the restriction above)
+    T* c;     // result (used on level 0 of the tail only)
     int n;
+    int off;  // offset of this level's x in the LDS array
 };
 
 template <class T>
@@ -359,64 +385,117 @@ struct TailDesc {
     int nu, coarse_sweeps;
 };
 
-template <class T>
-__device__ inline void tail_coords(const LevelView<T>& L, int c, int& i, int& j, int& k)
+// x / d for 0 <= x < 2^22 and d > 0 from a float reciprocal, corrected to the
+// exact quotient (the estimate is off by at most one).
+__device__ inline int qdiv(int x, int d, float inv)
 {
-    const int pl = L.nx * L.ny;
-    k = c / pl;
-    const int r = c - k * pl;
-    j = r / L.nx;
-    i = r - j * L.nx;
+    int q = (int)((float)x * inv);
+    const int r = x - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
 }
 
-// red-black SOR half-sweep of one colour over a whole level, by the whole block
+// Cells of a level with even nx taken in x-pairs (2m, 2m+1): pair t -> (m, j, k).
+struct PairIdx {
+    int hx, ny;
+    float inv_hx, inv_ny;
+};
 template <class T>
-__device__ inline void tail_half(const LevelView<T>& L, const T* f, T* x, int n, int colour, T omega)
+__device__ inline PairIdx pair_idx(const LevelView<T>& L)
 {
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        int i, j, k;
-        tail_coords(L, c, i, j, k);
+    return {L.nx >> 1, L.ny, 1.0f / (float)(L.nx >> 1), 1.0f / (float)L.ny};
+}
+__device__ inline void pair_coords(const PairIdx& P, int t, int& m, int& j, int& k)
+{
+    const int row = qdiv(t, P.hx, P.inv_hx);
+    m = t - row * P.hx;
+    k = qdiv(row, P.ny, P.inv_ny);
+    j = row - k * P.ny;
+}
+
+// Red-black SOR half-sweep of one colour over a level with even nx, x in LDS:
+// each thread visits only cells of the colour (one per x-pair).
+template <class T>
+__device__ inline void tail_half(const LevelView<T>& L, const T* __restrict__ f, T* xs, int colour, T omega)
+{
+    const PairIdx P = pair_idx(L);
+    const int np = P.hx * L.ny * L.nz;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < np; t += kTailThreads) {
+        int m, j, k;
+        pair_coords(P, t, m, j, k);
+        const int i = 2 * m + ((j + k + colour) & 1);
+        const int c = cell(L.nx, L.ny, i, j, k);
+        T s, d;
+        nbsum<T>(L, i, j, k, c, [&](int q, int, int, int) { return xs[q]; }, s, d);
+        T xv = (s + f[c]) * L.invd[c];
+        if (omega != T(1)) xv = xs[c] + omega * (xv - xs[c]);
+        xs[c] = xv;
+    }
+    __syncthreads();
+}
+
+// The same for any nx (the coarsest level when it is smoothed instead of solved).
+template <class T>
+__device__ inline void tail_half_any(const LevelView<T>& L, const T* __restrict__ f, T* xs, int n, int colour, T omega)
+{
+    const float inv_nx = 1.0f / (float)L.nx, inv_ny = 1.0f / (float)L.ny;
+    for (int c = threadIdx.x; c < n; c += kTailThreads) {
+        const int row = qdiv(c, L.nx, inv_nx);
+        const int i = c - row * L.nx;
+        const int k = qdiv(row, L.ny, inv_ny);
+        const int j = row - k * L.ny;
         if (((i + j + k) & 1) != colour) continue;
         T s, d;
-        nbsum<T>(L, i, j, k, c, [&](int m, int, int, int) { return x[m]; }, s, d);
+        nbsum<T>(L, i, j, k, c, [&](int q, int, int, int) { return xs[q]; }, s, d);
         T xv = (s + f[c]) * L.invd[c];
-        if (omega != T(1)) xv = x[c] + omega * (xv - x[c]);
-        x[c] = xv;
+        if (omega != T(1)) xv = xs[c] + omega * (xv - xs[c]);
+        xs[c] = xv;
     }
     __syncthreads();
 }
 
 // One V-cycle over the levels of D (each small enough for one block), from a
 // zero guess at the top; the result is left in D.L[0].c.  Same smoothing,
-// transfers and coarse solve as the per-level kernels.
+// transfers and coarse solve as the per-level kernels.  The iterate of every
+// level lives in LDS; right-hand sides and operators are read from global
+// memory (L2-resident at these sizes).
 template <class T>
 __global__ void __launch_bounds__(kTailThreads) k_tail_vcycle(TailDesc<T> D)
 {
+    __shared__ T xs_all[kTailLdsCells];
     const int last = D.nlev - 1;
     for (int l = 0; l < last; ++l) {
         const TailLevel<T>& V = D.L[l];
-        // first sweep from zero: red = omega f/D, black from the red values on the fly
-        for (int c = threadIdx.x; c < V.n; c += blockDim.x) {
-            int i, j, k;
-            tail_coords(V.v, c, i, j, k);
-            if (((i + j + k) & 1) == 0) {
-                V.c[c] = D.omega * (V.rhs[c] * V.v.invd[c]);
-            } else {
-                T s, d;
-                nbsum<T>(V.v, i, j, k, c, [&](int m, int, int, int) { return D.omega * (V.rhs[m] * V.v.invd[m]); }, s, d);
-                V.c[c] = D.omega * ((s + V.rhs[c]) * V.v.invd[c]);
+        T* x = xs_all + V.off;
+        // first sweep from zero: red = omega f / D with black = 0, then a black half-sweep
+        {
+            const PairIdx P = pair_idx(V.v);
+            const int np = P.hx * V.v.ny * V.v.nz;
+#pragma unroll 4
+            for (int t = threadIdx.x; t < np; t += kTailThreads) {
+                int m, j, k;
+                pair_coords(P, t, m, j, k);
+                const int c0 = cell(V.v.nx, V.v.ny, 2 * m, j, k);
+                const int cr = c0 + ((j + k) & 1);
+                x[cr] = D.omega * (V.rhs[cr] * V.v.invd[cr]);
+                x[cr ^ 1] = T(0);  // c0 is even: the pair differs in the lowest bit
             }
+            __syncthreads();
+            tail_half(V.v, V.rhs, x, 1, D.omega);
         }
-        __syncthreads();
         for (int s = 1; s < D.nu; ++s) {
-            tail_half(V.v, V.rhs, V.c, V.n, 0, D.omega);
-            tail_half(V.v, V.rhs, V.c, V.n, 1, D.omega);
+            tail_half(V.v, V.rhs, x, 0, D.omega);
+            tail_half(V.v, V.rhs, x, 1, D.omega);
         }
         // residual restricted to the next level (sum of the 8 children)
         const TailLevel<T>& C = D.L[l + 1];
-        for (int cc = threadIdx.x; cc < C.n; cc += blockDim.x) {
-            int I, J, K;
-            tail_coords(C.v, cc, I, J, K);
+        const float inv_cx = 1.0f / (float)C.v.nx, inv_cy = 1.0f / (float)C.v.ny;
+        for (int cc = threadIdx.x; cc < C.n; cc += kTailThreads) {
+            const int row = qdiv(cc, C.v.nx, inv_cx);
+            const int I = cc - row * C.v.nx;
+            const int K = qdiv(row, C.v.ny, inv_cy);
+            const int J = row - K * C.v.ny;
             T acc = T(0);
             for (int dk = 0; dk < 2; ++dk)
                 for (int dj = 0; dj < 2; ++dj)
@@ -424,8 +503,8 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_vcycle(TailDesc<T> D)
                         const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
                         const int c = cell(V.v.nx, V.v.ny, i, j, k);
                         T s, d;
-                        nbsum<T>(V.v, i, j, k, c, [&](int m, int, int, int) { return V.c[m]; }, s, d);
-                        acc += V.rhs[c] - (d * V.c[c] - s);
+                        nbsum<T>(V.v, i, j, k, c, [&](int q, int, int, int) { return x[q]; }, s, d);
+                        acc += V.rhs[c] - (d * x[c] - s);
                     }
             C.rhs[cc] = acc;
         }
@@ -433,41 +512,52 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_vcycle(TailDesc<T> D)
     }
     {
         const TailLevel<T>& B = D.L[last];
+        T* x = xs_all + B.off;
         if (D.nd > 0) {
-            for (int r = threadIdx.x; r < D.nd; r += blockDim.x) {
+            for (int r = threadIdx.x; r < D.nd; r += kTailThreads) {
                 T acc = T(0);
                 for (int c = 0; c < D.nd; ++c) acc += D.Minv[c * D.nd + r] * B.rhs[c];
-                B.c[r] = acc;
+                x[r] = acc;
             }
             __syncthreads();
         } else {
-            for (int c = threadIdx.x; c < B.n; c += blockDim.x) B.c[c] = T(0);
+            for (int c = threadIdx.x; c < B.n; c += kTailThreads) x[c] = T(0);
             __syncthreads();
             for (int s = 0; s < D.coarse_sweeps; ++s) {
-                tail_half(B.v, B.rhs, B.c, B.n, 0, D.omega);
-                tail_half(B.v, B.rhs, B.c, B.n, 1, D.omega);
+                tail_half_any(B.v, B.rhs, x, B.n, 0, D.omega);
+                tail_half_any(B.v, B.rhs, x, B.n, 1, D.omega);
             }
             for (int s = 0; s < D.coarse_sweeps; ++s) {
-                tail_half(B.v, B.rhs, B.c, B.n, 1, D.omega);
-                tail_half(B.v, B.rhs, B.c, B.n, 0, D.omega);
+                tail_half_any(B.v, B.rhs, x, B.n, 1, D.omega);
+                tail_half_any(B.v, B.rhs, x, B.n, 0, D.omega);
             }
         }
     }
     for (int l = last - 1; l >= 0; --l) {
         const TailLevel<T>& V = D.L[l];
         const TailLevel<T>& C = D.L[l + 1];
-        // prolongation and correction of every cell, then black before red
-        for (int c = threadIdx.x; c < V.n; c += blockDim.x) {
-            int i, j, k;
-            tail_coords(V.v, c, i, j, k);
-            V.c[c] += D.wc * C.c[cell(C.v.nx, C.v.ny, i >> 1, j >> 1, k >> 1)];
+        T* x = xs_all + V.off;
+        const T* e = xs_all + C.off;
+        // prolongation and correction of every cell (both cells of an x-pair
+        // share the coarse parent), then black before red
+        const PairIdx P = pair_idx(V.v);
+        const int np = P.hx * V.v.ny * V.v.nz;
+#pragma unroll 4
+        for (int t = threadIdx.x; t < np; t += kTailThreads) {
+            int m, j, k;
+            pair_coords(P, t, m, j, k);
+            const int c0 = cell(V.v.nx, V.v.ny, 2 * m, j, k);
+            const T ev = D.wc * e[cell(C.v.nx, C.v.ny, m, j >> 1, k >> 1)];
+            x[c0] += ev;
+            x[c0 + 1] += ev;
         }
         __syncthreads();
         for (int s = 0; s < D.nu; ++s) {
-            tail_half(V.v, V.rhs, V.c, V.n, 1, D.omega);
-            tail_half(V.v, V.rhs, V.c, V.n, 0, D.omega);
+            tail_half(V.v, V.rhs, x, 1, D.omega);
+            tail_half(V.v, V.rhs, x, 0, D.omega);
         }
     }
+    for (int c = threadIdx.x; c < D.L[0].n; c += kTailThreads) D.L[0].c[c] = xs_all[D.L[0].off + c];
 }
 
 // ---------------------------------------------------------------- float64 outer pieces

@@ -1,0 +1,355 @@
+// pp_march.hpp -- plane-marching stencil kernels (gfx950).
+//
+// The same operations as the per-cell kernels in pp_kernels.hpp, organised so
+// that each array element is read from global memory about once per pass.  A
+// block of 256 threads owns a BX x BY tile of cells (BX = 64, 32, 16 or 8) and
+// walks a range of z planes.  The value the stencil needs at a neighbour (x,
+// the red-cell value of a first sweep, the new search direction, ...) is
+// formed once per cell: the z neighbours come from a three-plane register
+// queue of the thread's own column, the in-plane neighbours from a
+// double-buffered LDS copy of the current plane, and only threads on the tile
+// edge read a halo value from global memory.  The west and south face weights
+// of a cell are the east / north weights of its neighbours and come from LDS as
+// well; the lower z face weight is carried over from the previous plane.
+//
+// One barrier per plane: a thread writes LDS buffer (k - k0) & 1, and a buffer
+// is written again only two planes later, after every thread has passed the
+// barrier that follows its last read of it.  The barrier waits for LDS only
+// (not for the global loads in flight), and the global loads of plane k+1 are
+// issued before the barrier of plane k into the other of two register sets,
+// so a wavefront keeps one plane of loads outstanding while it works on the
+// current one.
+#pragma once
+#include "pp_kernels.hpp"
+
+namespace pp {
+
+template <class T>
+struct Stencil {
+    T s;  // sum_f W_f v_nb(f)
+    T d;  // sum_f W_f = D_c
+};
+
+struct None {};
+
+// LDS stores of this wavefront complete, then the work-group barrier.  Global
+// loads still in flight are not waited for (each is waited for where its
+// register is used).
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// An operation supplies
+//   Raw  load(c, i, j, k)  the global inputs of the stencil value at a cell,
+//   T    val(raw)          the stencil value formed from them,
+//   Ex   extra(c)          further per-cell inputs of apply,
+//   void apply(c, i, j, k, v_c, raw_c, ex, st, acc, active)
+// where st holds the stencil sums of val over the six neighbours of cell c.
+// Every thread of the block calls apply at every plane (active is false
+// outside the grid) so that apply may use wavefront shuffles.  val at a
+// neighbour must not be changed by the pass itself (the callers write other
+// arrays, or only cells of the colour that val is not read at).
+// Global inputs of one plane k of the tile: own face weights, apply's extras,
+// the halo neighbour values (raw) and halo weights, and the raw inputs at k+1.
+template <class T, class Raw, class Ex>
+struct PlaneRegs {
+    T wx, wy, wz, wxh, wyh;
+    Raw rx, ry, rn;
+    Ex ex;
+};
+
+template <class T, int BX, class Op, class Acc>
+__device__ inline void march(const LevelView<T>& L, int kper, Op& op, Acc& acc)
+{
+    using Raw = typename Op::Raw;
+    using Ex = typename Op::Ex;
+    using Regs = PlaneRegs<T, Raw, Ex>;
+    constexpr int BY = kBlock / BX;
+    static_assert(BX >= 2 && BY >= 2, "a thread is on at most one x edge and one y edge of the tile");
+    __shared__ T sv[2][BY][BX];
+    __shared__ T swx[2][BY][BX];
+    __shared__ T swy[2][BY][BX];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty;
+    const int k0 = blockIdx.z * kper, k1 = min(L.nz, k0 + kper);
+    const bool act = i < L.nx && j < L.ny;
+    const int sy = L.nx, sz = L.nx * L.ny;
+    // Every load is issued by every lane at an address inside the grid (threads
+    // outside it read the nearest cell, edge threads without a halo neighbour
+    // read their own cell) and unused values are discarded: each plane issues
+    // the same loads, so the compiler waits for exactly the ones it needs.
+    const int ic = min(i, L.nx - 1), jc = min(j, L.ny - 1);
+    const bool hx = act && ((tx == 0 && i > 0) || (tx == BX - 1 && i < L.nx - 1));
+    const bool hy = act && ((ty == 0 && j > 0) || (ty == BY - 1 && j < L.ny - 1));
+    const int oi = hx ? (tx == 0 ? -1 : 1) : 0;  // x offset of this thread's halo neighbour
+    const int oj = hy ? (ty == 0 ? -1 : 1) : 0;
+    const int owx = oi < 0 ? -1 : 0;             // the west face weight read from global memory
+    const int owy = oj < 0 ? -sy : 0;
+    const bool in_e = i < L.nx - 1, in_n = j < L.ny - 1;
+
+    auto fetch = [&](Regs& S, int k, int c) {
+        const int kt = k < L.nz - 1 ? k + 1 : 0;
+        S.wx = L.wx[c];
+        S.wy = L.wy[c];
+        S.wz = L.wz[c];
+        S.ex = op.extra(c);
+        S.rn = op.load(c + (kt - k) * sz, ic, jc, kt);
+        S.rx = op.load(c + oi, ic + oi, jc, k);
+        S.ry = op.load(c + oj * sy, ic, jc + oj, k);
+        S.wxh = L.wx[c + owx];
+        S.wyh = L.wy[c + owy];
+    };
+
+    // prologue: value at k0-1, value and raw inputs at k0, registers of plane k0
+    const int kb0 = k0 > 0 ? k0 - 1 : L.nz - 1;
+    int c = cell(L.nx, L.ny, ic, jc, k0);
+    const T vm0 = op.val(op.load(c + (kb0 - k0) * sz, ic, jc, kb0));
+    T wzb = L.wz[c + (kb0 - k0) * sz];
+    Raw rc = op.load(c, ic, jc, k0);
+    Regs A, B;
+    fetch(A, k0, c);
+    T vm = act ? vm0 : T(0);
+    T vc = act ? op.val(rc) : T(0);
+
+    // One plane: S holds plane k, N receives plane k+1 (plane k again on the
+    // block's last plane, unused).
+    auto step = [&](Regs& S, Regs& N, int k, int c, int buf) {
+        const bool more = k + 1 < k1;
+        fetch(N, more ? k + 1 : k, more ? c + sz : c);
+        const T vp = act ? op.val(S.rn) : T(0);
+        const T vxh = hx ? op.val(S.rx) : T(0);
+        const T vyh = hy ? op.val(S.ry) : T(0);
+        sv[buf][ty][tx] = vc;
+        swx[buf][ty][tx] = act ? S.wx : T(0);
+        swy[buf][ty][tx] = act ? S.wy : T(0);
+        lds_barrier();
+        const T vw = tx > 0 ? sv[buf][ty][tx - 1] : vxh;
+        const T ve = tx < BX - 1 ? (in_e ? sv[buf][ty][tx + 1] : T(0)) : vxh;
+        const T vs = ty > 0 ? sv[buf][ty - 1][tx] : vyh;
+        const T vn = ty < BY - 1 ? (in_n ? sv[buf][ty + 1][tx] : T(0)) : vyh;
+        const T ww = i > 0 ? (tx > 0 ? swx[buf][ty][tx - 1] : S.wxh) : T(0);
+        const T ws = j > 0 ? (ty > 0 ? swy[buf][ty - 1][tx] : S.wyh) : T(0);
+        Stencil<T> st;
+        st.s = ww * vw + S.wx * ve + ws * vs + S.wy * vn + wzb * vm + S.wz * vp;
+        st.d = ww + S.wx + ws + S.wy + wzb + S.wz;
+        op.apply(c, i, j, k, vc, rc, S.ex, st, acc, act);
+        vm = vc;
+        vc = vp;
+        rc = S.rn;
+        wzb = S.wz;
+    };
+
+    // two planes per trip so that the register sets alternate without copies
+    int k = k0;
+    for (; k + 1 < k1; k += 2, c += 2 * sz) {
+        step(A, B, k, c, 0);
+        step(B, A, k + 1, c + sz, 1);
+    }
+    if (k < k1) step(A, B, k, c, 0);
+}
+
+// ---------------------------------------------------------------- operations
+
+template <class T>
+struct OpFirst {  // red-black SOR from a zero guess (red omega f/D, black one update)
+    const T *f, *invd;
+    T* x;
+    T omega;
+    struct Raw { T f, invd; };
+    using Ex = None;
+    __device__ Raw load(int c, int, int, int) const { return {f[c], invd[c]}; }
+    __device__ T val(const Raw& a) const { return omega * (a.f * a.invd); }
+    __device__ Ex extra(int) const { return {}; }
+    template <class A>
+    __device__ void apply(int c, int i, int j, int k, T vc, const Raw& a, const Ex&, const Stencil<T>& st, A&, bool act) const
+    {
+        if (!act) return;
+        x[c] = (((i + j + k) & 1) == 0) ? vc : omega * ((st.s + a.f) * a.invd);
+    }
+};
+
+template <class T, int NDOT, class TQ>
+struct OpHalf {  // one colour of a red-black SOR sweep in place; optional dots
+    const T *f, *invd;
+    T* x;
+    const TQ* q;
+    int colour;
+    T omega;
+    using Raw = T;
+    struct Ex { T f, invd; TQ q; };
+    __device__ Raw load(int c, int, int, int) const { return x[c]; }
+    __device__ T val(Raw a) const { return a; }
+    __device__ Ex extra(int c) const { return {f[c], invd[c], NDOT >= 2 ? q[c] : TQ(0)}; }
+    template <class A>
+    __device__ void apply(int c, int i, int j, int k, T vc, Raw, const Ex& e, const Stencil<T>& st, A& acc, bool act) const
+    {
+        if (!act) return;
+        T xv = vc;
+        if (((i + j + k) & 1) == colour) {
+            xv = (st.s + e.f) * e.invd;
+            if (omega != T(1)) xv = vc + omega * (xv - vc);
+            x[c] = xv;
+        }
+        if constexpr (NDOT >= 1) acc[0] += (double)xv;
+        if constexpr (NDOT >= 2) acc[1] += (double)xv * (double)e.q;
+    }
+};
+
+template <class T>
+struct OpProlongBlack {  // y = x + wc P e on red cells; black SOR update from them
+    const T *f, *invd, *x, *e;
+    T* y;
+    T wc, omega;
+    int cnx, cny;
+    struct Raw { T x, e; };
+    struct Ex { T f, invd; };
+    __device__ Raw load(int c, int i, int j, int k) const { return {x[c], e[cell(cnx, cny, i >> 1, j >> 1, k >> 1)]}; }
+    __device__ T val(const Raw& a) const { return a.x + wc * a.e; }
+    __device__ Ex extra(int c) const { return {f[c], invd[c]}; }
+    template <class A>
+    __device__ void apply(int c, int i, int j, int k, T vc, const Raw&, const Ex& ex, const Stencil<T>& st, A&, bool act) const
+    {
+        if (!act) return;
+        if (((i + j + k) & 1) == 0) {
+            y[c] = vc;
+        } else {
+            T gs = (st.s + ex.f) * ex.invd;
+            if (omega != T(1)) gs = vc + omega * (gs - vc);
+            y[c] = gs;
+        }
+    }
+};
+
+template <class T, class TZ, bool BETA>
+struct OpDir {  // d_new = (z - m) + b d_old (d_new = z - m without BETA), q = K d_new; dots <d,q>, <d,r>
+    const TZ* z;
+    const T* dold;
+    const T* r;
+    T* dnew;
+    T* q;
+    T b, m;
+    struct Raw { TZ z; T d; };
+    using Ex = T;
+    __device__ Raw load(int c, int, int, int) const { return {z[c], BETA ? dold[c] : T(0)}; }
+    __device__ T val(const Raw& a) const { return BETA ? ((T)a.z - m) + b * a.d : ((T)a.z - m); }
+    __device__ Ex extra(int c) const { return r[c]; }
+    template <class A>
+    __device__ void apply(int c, int, int, int, T vc, const Raw&, Ex rv, const Stencil<T>& st, A& acc, bool act) const
+    {
+        if (!act) return;
+        const T qc = st.d * vc - st.s;
+        dnew[c] = vc;
+        q[c] = qc;
+        acc[0] += (double)vc * (double)qc;
+        acc[1] += (double)vc * (double)rv;
+    }
+};
+
+template <class T>
+struct OpResidual {  // r = f - K x; dots ||r||^2, sum r
+    const T* f;
+    const T* x;
+    T* r;
+    using Raw = T;
+    using Ex = T;
+    __device__ Raw load(int c, int, int, int) const { return x[c]; }
+    __device__ T val(Raw a) const { return a; }
+    __device__ Ex extra(int c) const { return f[c]; }
+    template <class A>
+    __device__ void apply(int c, int, int, int, T vc, Raw, Ex fc, const Stencil<T>& st, A& acc, bool act) const
+    {
+        if (!act) return;
+        const T rv = fc - (st.d * vc - st.s);
+        r[c] = rv;
+        acc[0] += (double)rv * (double)rv;
+        acc[1] += (double)rv;
+    }
+};
+
+// Residual f - K x summed over the 8 children of each coarse cell.  The 2 x 2
+// children of a plane sit on lanes (l, l+1) of rows (ty, ty+1), which share a
+// wavefront for BX <= 32; the two planes of a pair are consecutive steps of the
+// march (the block's first plane and kper are even).
+template <class T, int BX>
+struct OpRestrict {
+    const T* f;
+    const T* x;
+    T* rc;
+    int cnx, cny, k0;
+    T part;
+    using Raw = T;
+    using Ex = T;
+    __device__ Raw load(int c, int, int, int) const { return x[c]; }
+    __device__ T val(Raw a) const { return a; }
+    __device__ Ex extra(int c) const { return f[c]; }
+    template <class A>
+    __device__ void apply(int c, int i, int j, int k, T vc, Raw, Ex fc, const Stencil<T>& st, A&, bool act)
+    {
+        const T rv = act ? fc - (st.d * vc - st.s) : T(0);
+        T p = rv + __shfl_down(rv, 1, 64);
+        p = p + __shfl_down(p, BX, 64);
+        if (((k - k0) & 1) == 0) part = p;
+        else if (act && ((threadIdx.x | threadIdx.y) & 1) == 0) rc[cell(cnx, cny, i >> 1, j >> 1, k >> 1)] = part + p;
+    }
+};
+
+// ---------------------------------------------------------------- kernels
+
+template <class T, int BX>
+__global__ void __launch_bounds__(kBlock) m_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
+                                                        T omega)
+{
+    OpFirst<T> op{f, L.invd, x, omega};
+    double acc[1] = {0.0};
+    march<T, BX>(L, kper, op, acc);
+}
+
+template <class T, int BX, int NDOT, class TQ>
+__global__ void __launch_bounds__(kBlock) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
+                                                       const TQ* __restrict__ q, Reduce R, T omega)
+{
+    OpHalf<T, NDOT, TQ> op{f, L.invd, x, q, colour, omega};
+    double acc[NDOT > 0 ? NDOT : 1] = {};
+    march<T, BX>(L, kper, op, acc);
+    if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
+}
+
+template <class T, int BX>
+__global__ void __launch_bounds__(kBlock) m_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
+                                                             T* __restrict__ rc, int kper)
+{
+    static_assert(BX <= 32, "the 2x2 sum pairs rows within one wavefront");
+    OpRestrict<T, BX> op{f, x, rc, L.nx >> 1, L.ny >> 1, (int)blockIdx.z * kper, T(0)};
+    double acc[1] = {0.0};
+    march<T, BX>(L, kper, op, acc);
+}
+
+template <class T, int BX>
+__global__ void __launch_bounds__(kBlock) m_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
+                                                         const T* __restrict__ e, T wc, T* __restrict__ y, int kper, T omega)
+{
+    OpProlongBlack<T> op{f, L.invd, x, e, y, wc, omega, L.nx >> 1, L.ny >> 1};
+    double acc[1] = {0.0};
+    march<T, BX>(L, kper, op, acc);
+}
+
+template <class T, int BX, class TZ, bool BETA>
+__global__ void __launch_bounds__(kBlock) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
+                                                     T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
+                                                     Coefs beta, Coefs mean, int use_mean, int kper, Reduce R)
+{
+    OpDir<T, TZ, BETA> op{z, dold, r, dnew, q, BETA ? (T)beta.get() : T(0), use_mean ? (T)mean.get() : T(0)};
+    double acc[2] = {0.0, 0.0};
+    march<T, BX>(L, kper, op, acc);
+    reduce_finish<2>(acc, R);
+}
+
+template <int BX>
+__global__ void __launch_bounds__(kBlock) m_true_residual(LevelView<double> L, const double* __restrict__ f,
+                                                         const double* __restrict__ x, double* __restrict__ r, int kper, Reduce R)
+{
+    OpResidual<double> op{f, x, r};
+    double acc[2] = {0.0, 0.0};
+    march<double, BX>(L, kper, op, acc);
+    reduce_finish<2>(acc, R);
+}
+
+}  // namespace pp

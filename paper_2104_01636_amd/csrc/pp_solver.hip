@@ -17,12 +17,20 @@
 // The preconditioner only changes the iteration count; the converged result is
 // the zero-mean solution of A p = b - mean(b).
 //
-// Mixed precision: in PP_FP32_REFINED mode the whole preconditioned Krylov
-// solve runs in float32 (dot products accumulate in float64) inside a float64
-// iterative-refinement loop: r = f - K x in float64, remove its mean, scale to
-// unit norm, solve K e = r in float32, x += s e in float64.  The outer
-// residual, the defect update and the final mean removal stay float64.
+// Mixed precision: in PP_FP32_REFINED mode the outer flexible CG stays
+// float64 (x, r, d, q and the operator built from rho), and only the
+// multigrid preconditioner runs in float32 on a float32 copy of r (dot
+// products accumulate in float64).  A preconditioner only has to be a fair
+// approximation of K^-1, so its rounding changes the iteration count, not the
+// accuracy reached; an iterative refinement with a float32 inner Krylov solve
+// instead stalls once kappa(K) * 2^-24 approaches one (kappa is about 1e7 for
+// a 128^2 x 256 grid with a 1000:1.2 density ratio).
+//
+// Stencil passes on levels with more cells than the single-workgroup tail use
+// the plane-marching kernels of pp_march.hpp (PP_MARCH=0 selects the simpler
+// one-thread-per-column kernels of pp_kernels.hpp, kept as a reference form).
 #include "pp_kernels.hpp"
+#include "pp_march.hpp"
 #include "../../include/pp.h"
 
 #include <algorithm>
@@ -72,6 +80,52 @@ static Geo geo(int nx, int ny, int nz, int max_blocks = kMaxRedBlocks)
     int kper = (nz + gz - 1) / gz;
     gz = (nz + kper - 1) / kper;
     return {dim3(gx, gy, gz), dim3(bx, by, 1), kper};
+}
+
+// Plane-march geometry: tiles of bx x (256 / bx) cells, bx a power of two in
+// [8, bx_max] not far above nx; z split so that the launch has at most
+// kMaxRedBlocks blocks; kper even when the kernel pairs planes.
+struct MGeo {
+    dim3 grid, block;
+    int kper, bx;
+};
+
+static MGeo mgeo(int nx, int ny, int nz, int bx_max, bool even_k = false, int max_blocks = kMaxRedBlocks)
+{
+    int bx = 8;
+    while (bx < nx && bx < bx_max) bx <<= 1;
+    const int by = kBlock / bx;
+    const int gx = (nx + bx - 1) / bx, gy = (ny + by - 1) / by;
+    const int tiles = gx * gy;
+    int gz = std::max(1, std::min(nz, max_blocks / std::max(1, tiles)));
+    int kper = (nz + gz - 1) / gz;
+    if (even_k && (kper & 1)) ++kper;
+    gz = (nz + kper - 1) / kper;
+    return {dim3(gx, gy, gz), dim3(bx, by, 1), kper, bx};
+}
+
+template <int B>
+using BxC = std::integral_constant<int, B>;
+
+// Calls f(BxC<bx>{}) for the tile widths the march kernels are built for.
+template <class F>
+static void with_bx(int bx, F&& f)
+{
+    switch (bx) {
+    case 8: f(BxC<8>{}); break;
+    case 16: f(BxC<16>{}); break;
+    case 32: f(BxC<32>{}); break;
+    default: f(BxC<64>{}); break;
+    }
+}
+template <class F>
+static void with_bx_le32(int bx, F&& f)
+{
+    switch (bx) {
+    case 8: f(BxC<8>{}); break;
+    case 16: f(BxC<16>{}); break;
+    default: f(BxC<32>{}); break;
+    }
 }
 
 static dim3 lin_grid(size_t n)
@@ -142,6 +196,9 @@ struct Params {
     bool graphs = true;
     double omega = 1.0;         // SOR factor of the red-black smoother
     bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
+    bool march = true;          // plane-marching stencil kernels (else one thread per cell column)
+    int mbx = 64;               // widest march tile in x
+    int mblocks = 1024;         // blocks of a march launch (at most; z split to reach it)
 };
 
 struct Handle {
@@ -183,7 +240,6 @@ struct Handle {
 
     // reductions
     double* partials = nullptr;
-    unsigned* counter = nullptr;
     double* slots = nullptr;
     double* host_slots = nullptr;  // pinned
 
@@ -292,7 +348,12 @@ static bool valid_cfg(const pp_config* cfg, std::string* why)
     if ((size_t)cfg->nx * cfg->ny * cfg->nz > (size_t)1 << 31) { if (why) *why = "grid too large"; return false; }
     {
         Geo g = geo(cfg->nx, cfg->ny, cfg->nz);
-        if ((size_t)g.grid.x * g.grid.y * g.grid.z > (size_t)kMaxRedBlocks) {
+        size_t most = (size_t)g.grid.x * g.grid.y * g.grid.z;
+        for (int b : {8, 16, 32, 64}) {
+            MGeo m = mgeo(cfg->nx, cfg->ny, cfg->nz, b);
+            most = std::max(most, (size_t)m.grid.x * m.grid.y * m.grid.z);
+        }
+        if (most > (size_t)kMaxRedBlocks) {
             if (why) *why = "cross-section too large (more than 2048 thread tiles per plane)";
             return false;
         }
@@ -390,7 +451,6 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     if (fp64) h64.L[0].rhs = r64;
     else h32.L[0].rhs = r32;
     double* partials = P.take<double>((size_t)kMaxRedBlocks * kMaxRed);
-    unsigned* counter = P.take<unsigned>(64);
     double* slots = P.take<double>(kSlots);
 
     if (H && base) {
@@ -399,7 +459,7 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         H->dense_work = dense_work; H->M64 = M64; H->M32 = M32;
         H->f64 = f64; H->r64 = r64; H->x64 = x64; H->q64 = q64; H->r32 = r32;
         H->d = H->d_a = d_a; H->d2 = H->d_b = d_b;
-        H->partials = partials; H->counter = counter; H->slots = slots;
+        H->partials = partials; H->slots = slots;
         // operator views
         for (int l = 0; l < nl; ++l) {
             h64.L[l].v = LevelView<double>{nx[l], ny[l], nz[l], c64[l].wx, c64[l].wy, c64[l].wz, c64[l].invd};
@@ -408,18 +468,27 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         auto make_tail = [&](auto& Hh) {
             Hh.tail = -1;
             if (!prm.tail || nl < 2) return;
+            // levels that fit: small enough, x-pairs above the last level, all iterates in LDS
             int t = nl - 1;
-            while (t - 1 >= 1 && !Hh.L[t - 1].kcyc && Hh.L[t - 1].n <= (size_t)kTailMaxCells) --t;
+            size_t cells = Hh.L[t].n;
+            while (t - 1 >= 1 && !Hh.L[t - 1].kcyc && Hh.L[t - 1].n <= (size_t)kTailMaxCells &&
+                   (Hh.L[t - 1].nx % 2) == 0 && cells + Hh.L[t - 1].n <= (size_t)kTailLdsCells) {
+                --t;
+                cells += Hh.L[t].n;
+            }
             if (t == nl - 1 || t <= prm.kmax || nl - t > kTailMaxLev) return;  // need at least two levels
             Hh.tail = t;
             auto& D = Hh.td;
             D.nlev = nl - t;
+            int off = 0;
             for (int l = t; l < nl; ++l) {
                 auto& V = Hh.L[l];
                 D.L[l - t].v = V.v;
                 D.L[l - t].rhs = V.rhs;
                 D.L[l - t].c = V.c;
                 D.L[l - t].n = (int)V.n;
+                D.L[l - t].off = off;
+                off += (int)V.n;
             }
             D.Minv = Hh.Minv;
             D.nd = Hh.nd;
@@ -442,11 +511,11 @@ static Reduce red(Handle* H, int s0, int s1 = 0, int s2 = 0, int s3 = 0)
 {
     Reduce R;
     R.partials = H->partials;
-    R.counter = H->counter;
     R.out = H->slots;
     R.slot[0] = s0; R.slot[1] = s1; R.slot[2] = s2; R.slot[3] = s3;
     return R;
 }
+
 static Coefs coef(Handle* H, int num, int den, double sign) { return Coefs{H->slots, num, den, sign}; }
 
 // Work of an entry point runs on the handle's stream, after everything queued
@@ -468,6 +537,13 @@ static void check_launch()
     if (e != hipSuccess) throw Fail(PP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
+// Completes a reducing launch with the given grid: its nv totals land in the slots.
+static void finish(Handle* H, const Reduce& R, const dim3& grid, int nv)
+{
+    k_reduce_finish<<<1, kBlock, 0, H->stream>>>(R, (int)(grid.x * grid.y * grid.z), nv);
+    check_launch();
+}
+
 static void read_slots(Handle* H, int first, int count)
 {
     PP_HIP(hipMemcpyAsync(H->host_slots + first, H->slots + first, sizeof(double) * count, hipMemcpyDeviceToHost, H->stream));
@@ -485,18 +561,111 @@ static void write_slots(Handle* H, int first, const double* v, int count)
 template <class T>
 static int kid(int id) { return id + (sizeof(T) == 4 ? 0 : 32); }
 
+// Launchers: the plane-march kernels, or the per-column kernels when the march is off.
+
+template <class T>
+static void launch_first(Handle* H, const LevelView<T>& v, const T* f, T* x)
+{
+    const T om = (T)H->prm.omega;
+    if (H->prm.march) {
+        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        with_bx(g.bx, [&](auto B) {
+            m_smooth_first<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, g.kper, om);
+        });
+    } else {
+        const Geo g = geo(v.nx, v.ny, v.nz);
+        k_smooth_first<T><<<g.grid, g.block, 0, H->stream>>>(v, f, x, g.kper, om);
+    }
+    check_launch();
+}
+
+// Launchers of reducing kernels return the grid; the caller completes the
+// reduction with finish() (outside any timed scope).
+template <class T, int NDOT, class TQ>
+static dim3 launch_half(Handle* H, const LevelView<T>& v, const T* f, T* x, int colour, const TQ* q, const Reduce& R)
+{
+    const T om = (T)H->prm.omega;
+    if (H->prm.march) {
+        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        with_bx(g.bx, [&](auto B) {
+            m_smooth_half<T, decltype(B)::value, NDOT, TQ><<<g.grid, g.block, 0, H->stream>>>(v, f, x, colour, g.kper, q, R, om);
+        });
+        check_launch();
+        return g.grid;
+    }
+    const Geo g = geo(v.nx, v.ny, v.nz);
+    k_smooth_half<T, NDOT, TQ><<<g.grid, g.block, 0, H->stream>>>(v, f, x, colour, g.kper, q, R, om);
+    check_launch();
+    return g.grid;
+}
+
+template <class T>
+static void launch_restrict(Handle* H, const LevelView<T>& v, const T* f, const T* x, T* rc)
+{
+    if (H->prm.march) {
+        const MGeo g = mgeo(v.nx, v.ny, v.nz, std::min(H->prm.mbx, 32), true, H->prm.mblocks);
+        with_bx_le32(g.bx, [&](auto B) {
+            m_residual_restrict<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper);
+        });
+    } else {
+        const Geo g = geo(v.nx / 2, v.ny / 2, v.nz / 2);
+        k_residual_restrict<T><<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, v.nx / 2, v.ny / 2, v.nz / 2, g.kper);
+    }
+    check_launch();
+}
+
+template <class T>
+static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, const T* x, const T* e, T wc, T* y)
+{
+    const T om = (T)H->prm.omega;
+    if (H->prm.march) {
+        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        with_bx(g.bx, [&](auto B) {
+            m_prolong_black<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, e, wc, y, g.kper, om);
+        });
+    } else {
+        const Geo g = geo(v.nx, v.ny, v.nz);
+        k_prolong_black<T><<<g.grid, g.block, 0, H->stream>>>(v, f, x, e, wc, y, g.kper, om);
+    }
+    check_launch();
+}
+
+template <class T, class TZ>
+static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* dold, T* dnew, T* q, const T* r, Coefs beta,
+                       int use_beta, Coefs mean, int use_mean, const Reduce& R)
+{
+    if (H->prm.march) {
+        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        with_bx(g.bx, [&](auto B) {
+            constexpr int BX = decltype(B)::value;
+            if (use_beta)
+                m_dir_apply<T, BX, TZ, true><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper, R);
+            else
+                m_dir_apply<T, BX, TZ, false><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper, R);
+        });
+        check_launch();
+        return g.grid;
+    }
+    const Geo g = geo(v.nx, v.ny, v.nz);
+    k_dir_apply<T, TZ><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, use_beta, mean, use_mean, g.kper, R);
+    check_launch();
+    return g.grid;
+}
+
 template <class T, class TQ>
 static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int colour, int ndot, const TQ* q, int l)
 {
-    Geo g = geo(V.nx, V.ny, V.nz);
     Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
-    // reads x, f, three face arrays and 1/D; writes one colour (and reads q for the dot)
-    TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
-                 (double)V.n * (6.5 * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
-    if (ndot == 0) k_smooth_half<T, 0, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-    else if (ndot == 1) k_smooth_half<T, 1, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-    else k_smooth_half<T, 2, TQ><<<g.grid, g.block, 0, H->stream>>>(V.v, f, x, colour, g.kper, q, R, (T)H->prm.omega);
-    check_launch();
+    dim3 grid;
+    {
+        // reads x, f, three face arrays and 1/D; writes one colour (and reads q for the dot)
+        TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
+                     (double)V.n * (6.5 * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
+        if (ndot == 0) grid = launch_half<T, 0, TQ>(H, V.v, f, x, colour, q, R);
+        else if (ndot == 1) grid = launch_half<T, 1, TQ>(H, V.v, f, x, colour, q, R);
+        else grid = launch_half<T, 2, TQ>(H, V.v, f, x, colour, q, R);
+    }
+    if (ndot > 0) finish(H, R, grid, ndot);
 }
 
 template <class T>
@@ -523,12 +692,10 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         } else {
             // symmetric block of red-black sweeps (also the whole cycle when the
             // finest level cannot be coarsened)
-            Geo g = geo(V.nx, V.ny, V.nz);
             {
                 TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 6.0);
-                k_smooth_first<T><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
+                launch_first<T>(H, V.v, f, V.c);
             }
-            check_launch();
             const int ns = H->prm.coarse_sweeps;
             for (int s = 1; s < ns; ++s) {
                 smooth_half(H, V, fine, f, V.c, 0, 0, (const T*)nullptr, l);
@@ -542,25 +709,21 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         return V.c;
     }
     const int nu = fine ? H->prm.nu0 : H->prm.nuc;
-    Geo g = geo(V.nx, V.ny, V.nz);
     {
         // reads f, three face arrays and 1/D; writes x
         TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 6.0);
-        k_smooth_first<T><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, g.kper, (T)H->prm.omega);
+        launch_first<T>(H, V.v, f, V.c);
     }
-    check_launch();
     for (int s = 1; s < nu; ++s) {
         smooth_half(H, V, fine, f, V.c, 0, 0, (const T*)nullptr, l);
         smooth_half(H, V, fine, f, V.c, 1, 0, (const T*)nullptr, l);
     }
     Lev<T>& C = Hh.L[l + 1];
-    Geo gc = geo(C.nx, C.ny, C.nz);
     {
         // reads x, f and three face arrays; writes the coarse right-hand side
         TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (5.0 + 0.125));
-        k_residual_restrict<T><<<gc.grid, gc.block, 0, H->stream>>>(V.v, f, V.c, C.rhs, C.nx, C.ny, C.nz, gc.kper);
+        launch_restrict<T>(H, V.v, f, V.c, C.rhs);
     }
-    check_launch();
     T* e;
     T wc;
     if (C.kcyc) {
@@ -573,9 +736,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     {
         // reads x, f, three face arrays, 1/D and the coarse correction; writes y
         TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (7.0 + 0.125));
-        k_prolong_black<T><<<g.grid, g.block, 0, H->stream>>>(V.v, f, V.c, e, wc, V.c2, g.kper, (T)H->prm.omega);
+        launch_prolong_black<T>(H, V.v, f, V.c, e, wc, V.c2);
     }
-    check_launch();
     T* cur = V.c2;
     for (int s = 0; s < nu; ++s) {
         if (s > 0) smooth_half(H, V, fine, f, cur, 1, 0, (const T*)nullptr, l);
@@ -587,14 +749,12 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
 template <class T>
 static void dir_apply(Handle* H, Lev<T>& V, bool fine, const T* z, int it, int l, bool mean)
 {
-    Geo g = geo(V.nx, V.ny, V.nz);
     const int dq_prev = lslot(l, (it & 1) ? S_DQ0 : S_DQ1);
     const int dq_cur = lslot(l, (it & 1) ? S_DQ1 : S_DQ0);
     Coefs beta = coef(H, lslot(l, S_ZQ), dq_prev, -1.0);
     Coefs mn = coef(H, lslot(l, S_SUMZ), -1, 1.0 / (double)V.n);
     Reduce R = red(H, dq_cur, lslot(l, S_DR));
-    k_dir_apply<T><<<g.grid, g.block, 0, H->stream>>>(V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, g.kper, R);
-    check_launch();
+    finish(H, R, launch_dir<T, T>(H, V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, R), 2);
 }
 
 template <class T>
@@ -602,9 +762,11 @@ static void update_xr(Handle* H, Lev<T>& V, T* x, int it, int l, bool first, boo
 {
     const int dq_cur = lslot(l, (it & 1) ? S_DQ1 : S_DQ0);
     Coefs alpha = coef(H, lslot(l, S_DR), dq_cur, 1.0);
-    k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>((int)V.n, x, V.d2, V.rhs, V.q, alpha, first, skip_r, want,
-                                                         red(H, lslot(l, S_RR), lslot(l, S_RSUM)), (float*)nullptr);
+    const Reduce R = red(H, lslot(l, S_RR), lslot(l, S_RSUM));
+    k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>((int)V.n, x, V.d2, V.rhs, V.q, alpha, first, skip_r, want, R,
+                                                         (float*)nullptr);
     check_launch();
+    if (want) finish(H, R, lin_grid(V.n), 2);
 }
 
 // K-cycle: kit flexible-CG steps on K_l x = rhs_l (rhs_l is used as the residual).
@@ -635,25 +797,30 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
     const pp_config& cfg = H->cfg;
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, k > 0 ? 2 : 1, H->q64);
+    const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
+    const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
     {
-        Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
-        const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
-        const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
         const LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
-        // reads z, d_old, three float64 face arrays and r; writes d and q
-        TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 64.0 : 56.0)));
-        k_dir_apply<double, P><<<g.grid, g.block, 0, H->stream>>>(
-            v, z, H->d, H->d2, H->q64, H->r64, coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
-            coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1, g.kper, red(H, dq_cur, lslot(0, S_DR)));
-        check_launch();
+        const Reduce R = red(H, dq_cur, lslot(0, S_DR));
+        dim3 grid;
+        {
+            // reads z, d_old, three float64 face arrays and r; writes d and q
+            TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 64.0 : 56.0)));
+            grid = launch_dir<double, P>(H, v, z, H->d, H->d2, H->q64, H->r64, coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
+                                         coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1, R);
+        }
+        finish(H, R, grid, 2);
     }
     {
-        const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
-        TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (48.0 + (H->r32 ? 4.0 : 0.0)));
-        k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
-                                                                    coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1,
-                                                                    red(H, lslot(0, S_RR), lslot(0, S_RSUM)), H->r32);
-        check_launch();
+        const Reduce R = red(H, lslot(0, S_RR), lslot(0, S_RSUM));
+        {
+            // reads x, d, r and q; writes x, r and the float32 copy of r
+            TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (48.0 + (H->r32 ? 4.0 : 0.0)));
+            k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
+                                                                        coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1, R, H->r32);
+            check_launch();
+        }
+        finish(H, R, lin_grid(n0), 2);
     }
     std::swap(H->d, H->d2);
 }
@@ -736,6 +903,7 @@ static void set_density(Handle* H, const double* rho)
     // validate: finite and > 0
     k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, 1, red(H, G_RHOSUM, G_RHOBAD));
     check_launch();
+    finish(H, red(H, G_RHOSUM, G_RHOBAD), lin_grid(n0), 2);
     read_slots(H, G_RHOSUM, 2);
     if (H->host_slots[G_RHOBAD] != 0.0)
         throw Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
@@ -776,12 +944,14 @@ static double prepare_rhs(Handle* H, const double* rhs)
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, 0, red(H, G_BSUM, G_BBAD));
     check_launch();
+    finish(H, red(H, G_BSUM, G_BBAD), lin_grid(n0), 2);
     read_slots(H, G_BSUM, 2);
     if (H->host_slots[G_BBAD] != 0.0)
         throw Fail(PP_ERR_NONFINITE, "rhs has " + std::to_string((long long)H->host_slots[G_BBAD]) + " non-finite entries");
     k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, H->f64, -cfg.h * cfg.h, coef(H, G_BSUM, -1, 1.0 / (double)n0),
                                                           1, red(H, G_FN2));
     check_launch();
+    finish(H, red(H, G_FN2), lin_grid(n0), 1);
     read_slots(H, G_FN2, 1);
     return std::sqrt(H->host_slots[G_FN2]);
 }
@@ -790,11 +960,27 @@ static double prepare_rhs(Handle* H, const double* rhs)
 static double true_residual(Handle* H, const double* x)
 {
     const pp_config& cfg = H->cfg;
-    Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
     const LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
-    TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * 32.0);
-    k_true_residual<<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, red(H, G_TRR, G_TRSUM));
-    check_launch();
+    {
+        // reads f, x and three float64 face arrays; writes r
+        TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * 48.0);
+        const Reduce R = red(H, G_TRR, G_TRSUM);
+        if (H->prm.march) {
+            const MGeo g = mgeo(cfg.nx, cfg.ny, cfg.nz, H->prm.mbx, false, H->prm.mblocks);
+            with_bx(g.bx, [&](auto B) {
+                m_true_residual<decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, R);
+            });
+        } else {
+            const Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
+            k_true_residual<<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, R);
+        }
+        check_launch();
+    }
+    {
+        const dim3 grid = H->prm.march ? mgeo(cfg.nx, cfg.ny, cfg.nz, H->prm.mbx, false, H->prm.mblocks).grid
+                                       : geo(cfg.nx, cfg.ny, cfg.nz).grid;
+        finish(H, red(H, G_TRR, G_TRSUM), grid, 2);
+    }
     read_slots(H, G_TRR, 2);
     return std::sqrt(std::max(0.0, H->host_slots[G_TRR]));
 }
@@ -804,6 +990,7 @@ static void remove_mean(Handle* H, double* x)
     const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
     k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, 0, red(H, G_XSUM, G_XBAD));
     check_launch();
+    finish(H, red(H, G_XSUM, G_XBAD), lin_grid(n0), 2);
     k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, x, 1.0, coef(H, G_XSUM, -1, 1.0 / (double)n0), 0,
                                                           red(H, G_FN2));
     check_launch();
@@ -886,6 +1073,12 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
     if (const char* s = getenv("PP_TAIL")) p.tail = atoi(s) != 0;
+    if (const char* s = getenv("PP_MARCH")) p.march = atoi(s) != 0;
+    if (const char* s = getenv("PP_MBLOCKS")) p.mblocks = std::max(64, std::min(kMaxRedBlocks, atoi(s)));
+    if (const char* s = getenv("PP_MBX")) {
+        const int b = atoi(s);
+        p.mbx = (b >= 64) ? 64 : (b >= 32) ? 32 : (b >= 16) ? 16 : 8;
+    }
 }
 
 }  // namespace pp
@@ -959,7 +1152,6 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
         PP_HIP(hipHostMalloc((void**)&H->host_slots, sizeof(double) * kSlots, hipHostMallocDefault));
         PP_HIP(hipEventCreate(&H->ev0));
         PP_HIP(hipEventCreate(&H->ev1));
-        PP_HIP(hipMemsetAsync(H->counter, 0, 64 * sizeof(unsigned), H->stream));
         PP_HIP(hipMemsetAsync(H->slots, 0, kSlots * sizeof(double), H->stream));
         {
             double one = 1.0;
