@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--workload", default="duct256")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=20, help="oracle iterations in the CPU-baseline sample")
+    ap.add_argument("--cpu-iters", type=int, default=120, help="oracle iterations in the CPU-baseline sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware traffic counters)")
     ap.add_argument("--forms", default="fp32_refined,fp64")

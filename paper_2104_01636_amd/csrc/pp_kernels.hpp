@@ -359,207 +359,6 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restri
 }
 
 
-// ---------------------------------------------------------------- small coarse levels in one launch
-
-constexpr int kTailMaxLev = 12;
-constexpr int kTailThreads = 1024;
-constexpr int kTailMaxCells = 8192;   // levels at most this large run inside k_tail_vcycle
-constexpr int kTailLdsCells = 9400;   // x of every tail level stays in LDS (sum <= 8192 * 8/7)
-
-template <class T>
-struct TailLevel {
-    LevelView<T> v;
-    T* rhs;   // right-hand side (level 0 of the tail: written by the restriction above)
-    T* c;     // result (used on level 0 of the tail only)
-    int n;
-    int off;  // offset of this level's x in the LDS array
-};
-
-template <class T>
-struct TailDesc {
-    int nlev;
-    TailLevel<T> L[kTailMaxLev];
-    const T* Minv;  // dense inverse of the last level (nd > 0), else symmetric sweeps
-    int nd;
-    T wc, omega;
-    int nu, coarse_sweeps;
-};
-
-// x / d for 0 <= x < 2^22 and d > 0 from a float reciprocal, corrected to the
-// exact quotient (the estimate is off by at most one).
-__device__ inline int qdiv(int x, int d, float inv)
-{
-    int q = (int)((float)x * inv);
-    const int r = x - q * d;
-    q += (r >= d) - (r < 0);
-    return q;
-}
-
-// Cells of a level with even nx taken in x-pairs (2m, 2m+1): pair t -> (m, j, k).
-struct PairIdx {
-    int hx, ny;
-    float inv_hx, inv_ny;
-};
-template <class T>
-__device__ inline PairIdx pair_idx(const LevelView<T>& L)
-{
-    return {L.nx >> 1, L.ny, 1.0f / (float)(L.nx >> 1), 1.0f / (float)L.ny};
-}
-__device__ inline void pair_coords(const PairIdx& P, int t, int& m, int& j, int& k)
-{
-    const int row = qdiv(t, P.hx, P.inv_hx);
-    m = t - row * P.hx;
-    k = qdiv(row, P.ny, P.inv_ny);
-    j = row - k * P.ny;
-}
-
-// Red-black SOR half-sweep of one colour over a level with even nx, x in LDS:
-// each thread visits only cells of the colour (one per x-pair).
-template <class T>
-__device__ inline void tail_half(const LevelView<T>& L, const T* __restrict__ f, T* xs, int colour, T omega)
-{
-    const PairIdx P = pair_idx(L);
-    const int np = P.hx * L.ny * L.nz;
-#pragma unroll 4
-    for (int t = threadIdx.x; t < np; t += kTailThreads) {
-        int m, j, k;
-        pair_coords(P, t, m, j, k);
-        const int i = 2 * m + ((j + k + colour) & 1);
-        const int c = cell(L.nx, L.ny, i, j, k);
-        T s, d;
-        nbsum<T>(L, i, j, k, c, [&](int q, int, int, int) { return xs[q]; }, s, d);
-        T xv = (s + f[c]) * L.invd[c];
-        if (omega != T(1)) xv = xs[c] + omega * (xv - xs[c]);
-        xs[c] = xv;
-    }
-    __syncthreads();
-}
-
-// The same for any nx (the coarsest level when it is smoothed instead of solved).
-template <class T>
-__device__ inline void tail_half_any(const LevelView<T>& L, const T* __restrict__ f, T* xs, int n, int colour, T omega)
-{
-    const float inv_nx = 1.0f / (float)L.nx, inv_ny = 1.0f / (float)L.ny;
-    for (int c = threadIdx.x; c < n; c += kTailThreads) {
-        const int row = qdiv(c, L.nx, inv_nx);
-        const int i = c - row * L.nx;
-        const int k = qdiv(row, L.ny, inv_ny);
-        const int j = row - k * L.ny;
-        if (((i + j + k) & 1) != colour) continue;
-        T s, d;
-        nbsum<T>(L, i, j, k, c, [&](int q, int, int, int) { return xs[q]; }, s, d);
-        T xv = (s + f[c]) * L.invd[c];
-        if (omega != T(1)) xv = xs[c] + omega * (xv - xs[c]);
-        xs[c] = xv;
-    }
-    __syncthreads();
-}
-
-// One V-cycle over the levels of D (each small enough for one block), from a
-// zero guess at the top; the result is left in D.L[0].c.  Same smoothing,
-// transfers and coarse solve as the per-level kernels.  The iterate of every
-// level lives in LDS; right-hand sides and operators are read from global
-// memory (L2-resident at these sizes).
-template <class T>
-__global__ void __launch_bounds__(kTailThreads) k_tail_vcycle(TailDesc<T> D)
-{
-    __shared__ T xs_all[kTailLdsCells];
-    const int last = D.nlev - 1;
-    for (int l = 0; l < last; ++l) {
-        const TailLevel<T>& V = D.L[l];
-        T* x = xs_all + V.off;
-        // first sweep from zero: red = omega f / D with black = 0, then a black half-sweep
-        {
-            const PairIdx P = pair_idx(V.v);
-            const int np = P.hx * V.v.ny * V.v.nz;
-#pragma unroll 4
-            for (int t = threadIdx.x; t < np; t += kTailThreads) {
-                int m, j, k;
-                pair_coords(P, t, m, j, k);
-                const int c0 = cell(V.v.nx, V.v.ny, 2 * m, j, k);
-                const int cr = c0 + ((j + k) & 1);
-                x[cr] = D.omega * (V.rhs[cr] * V.v.invd[cr]);
-                x[cr ^ 1] = T(0);  // c0 is even: the pair differs in the lowest bit
-            }
-            __syncthreads();
-            tail_half(V.v, V.rhs, x, 1, D.omega);
-        }
-        for (int s = 1; s < D.nu; ++s) {
-            tail_half(V.v, V.rhs, x, 0, D.omega);
-            tail_half(V.v, V.rhs, x, 1, D.omega);
-        }
-        // residual restricted to the next level (sum of the 8 children)
-        const TailLevel<T>& C = D.L[l + 1];
-        const float inv_cx = 1.0f / (float)C.v.nx, inv_cy = 1.0f / (float)C.v.ny;
-        for (int cc = threadIdx.x; cc < C.n; cc += kTailThreads) {
-            const int row = qdiv(cc, C.v.nx, inv_cx);
-            const int I = cc - row * C.v.nx;
-            const int K = qdiv(row, C.v.ny, inv_cy);
-            const int J = row - K * C.v.ny;
-            T acc = T(0);
-            for (int dk = 0; dk < 2; ++dk)
-                for (int dj = 0; dj < 2; ++dj)
-                    for (int di = 0; di < 2; ++di) {
-                        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-                        const int c = cell(V.v.nx, V.v.ny, i, j, k);
-                        T s, d;
-                        nbsum<T>(V.v, i, j, k, c, [&](int q, int, int, int) { return x[q]; }, s, d);
-                        acc += V.rhs[c] - (d * x[c] - s);
-                    }
-            C.rhs[cc] = acc;
-        }
-        __syncthreads();
-    }
-    {
-        const TailLevel<T>& B = D.L[last];
-        T* x = xs_all + B.off;
-        if (D.nd > 0) {
-            for (int r = threadIdx.x; r < D.nd; r += kTailThreads) {
-                T acc = T(0);
-                for (int c = 0; c < D.nd; ++c) acc += D.Minv[c * D.nd + r] * B.rhs[c];
-                x[r] = acc;
-            }
-            __syncthreads();
-        } else {
-            for (int c = threadIdx.x; c < B.n; c += kTailThreads) x[c] = T(0);
-            __syncthreads();
-            for (int s = 0; s < D.coarse_sweeps; ++s) {
-                tail_half_any(B.v, B.rhs, x, B.n, 0, D.omega);
-                tail_half_any(B.v, B.rhs, x, B.n, 1, D.omega);
-            }
-            for (int s = 0; s < D.coarse_sweeps; ++s) {
-                tail_half_any(B.v, B.rhs, x, B.n, 1, D.omega);
-                tail_half_any(B.v, B.rhs, x, B.n, 0, D.omega);
-            }
-        }
-    }
-    for (int l = last - 1; l >= 0; --l) {
-        const TailLevel<T>& V = D.L[l];
-        const TailLevel<T>& C = D.L[l + 1];
-        T* x = xs_all + V.off;
-        const T* e = xs_all + C.off;
-        // prolongation and correction of every cell (both cells of an x-pair
-        // share the coarse parent), then black before red
-        const PairIdx P = pair_idx(V.v);
-        const int np = P.hx * V.v.ny * V.v.nz;
-#pragma unroll 4
-        for (int t = threadIdx.x; t < np; t += kTailThreads) {
-            int m, j, k;
-            pair_coords(P, t, m, j, k);
-            const int c0 = cell(V.v.nx, V.v.ny, 2 * m, j, k);
-            const T ev = D.wc * e[cell(C.v.nx, C.v.ny, m, j >> 1, k >> 1)];
-            x[c0] += ev;
-            x[c0 + 1] += ev;
-        }
-        __syncthreads();
-        for (int s = 0; s < D.nu; ++s) {
-            tail_half(V.v, V.rhs, x, 1, D.omega);
-            tail_half(V.v, V.rhs, x, 0, D.omega);
-        }
-    }
-    for (int c = threadIdx.x; c < D.L[0].n; c += kTailThreads) D.L[0].c[c] = xs_all[D.L[0].off + c];
-}
-
 // ---------------------------------------------------------------- float64 outer pieces
 
 // r = f - K x in float64; reduces ||r||^2 and sum(r).

@@ -32,6 +32,23 @@ struct Stencil {
 
 struct None {};
 
+// Tile of this block.  Blocks are dealt to the 8 XCDs round-robin (block b
+// runs on XCD b mod 8), and each XCD has its own L2.  So that tiles sharing
+// halo rows and columns share an L2, the b-th block takes tile
+// (b mod 8) * (nblocks / 8) + b / 8 in x-fastest order: every XCD works on a
+// contiguous run of tiles.  Launches whose block count is not a multiple of 8
+// (or with xcd = 0) keep the plain order.
+__device__ inline void tile_of_block(int& bx, int& by, int& bz, int xcd)
+{
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int nb = gx * gy * gridDim.z;
+    const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int t = (!xcd || (nb & 7)) ? b : (b & 7) * (nb >> 3) + (b >> 3);
+    bx = t % gx;
+    by = (t / gx) % gy;
+    bz = t / (gx * gy);
+}
+
 // LDS stores of this wavefront complete, then the work-group barrier.  Global
 // loads still in flight are not waited for (each is waited for where its
 // register is used).
@@ -57,7 +74,7 @@ struct PlaneRegs {
 };
 
 template <class T, int BX, class Op, class Acc>
-__device__ inline void march(const LevelView<T>& L, int kper, Op& op, Acc& acc)
+__device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, Acc& acc)
 {
     using Raw = typename Op::Raw;
     using Ex = typename Op::Ex;
@@ -68,8 +85,10 @@ __device__ inline void march(const LevelView<T>& L, int kper, Op& op, Acc& acc)
     __shared__ T swx[2][BY][BX];
     __shared__ T swy[2][BY][BX];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty;
-    const int k0 = blockIdx.z * kper, k1 = min(L.nz, k0 + kper);
+    int bx, by, bz;
+    tile_of_block(bx, by, bz, xcd);
+    const int i = bx * BX + tx, j = by * BY + ty;
+    const int k0 = bz * kper, k1 = min(L.nz, k0 + kper);
     const bool act = i < L.nx && j < L.ny;
     const int sy = L.nx, sz = L.nx * L.ny;
     // Every load is issued by every lane at an address inside the grid (threads
@@ -295,60 +314,64 @@ struct OpRestrict {
 
 template <class T, int BX>
 __global__ void __launch_bounds__(kBlock) m_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
-                                                        T omega)
+                                                        int xcd, T omega)
 {
     OpFirst<T> op{f, L.invd, x, omega};
     double acc[1] = {0.0};
-    march<T, BX>(L, kper, op, acc);
+    march<T, BX>(L, kper, xcd, op, acc);
 }
 
 template <class T, int BX, int NDOT, class TQ>
 __global__ void __launch_bounds__(kBlock) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
-                                                       const TQ* __restrict__ q, Reduce R, T omega)
+                                                       int xcd, const TQ* __restrict__ q, Reduce R, T omega)
 {
     OpHalf<T, NDOT, TQ> op{f, L.invd, x, q, colour, omega};
     double acc[NDOT > 0 ? NDOT : 1] = {};
-    march<T, BX>(L, kper, op, acc);
+    march<T, BX>(L, kper, xcd, op, acc);
     if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
 }
 
 template <class T, int BX>
 __global__ void __launch_bounds__(kBlock) m_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
-                                                             T* __restrict__ rc, int kper)
+                                                             T* __restrict__ rc, int kper, int xcd)
 {
     static_assert(BX <= 32, "the 2x2 sum pairs rows within one wavefront");
-    OpRestrict<T, BX> op{f, x, rc, L.nx >> 1, L.ny >> 1, (int)blockIdx.z * kper, T(0)};
+    int bx, by, bz;
+    tile_of_block(bx, by, bz, xcd);
+    OpRestrict<T, BX> op{f, x, rc, L.nx >> 1, L.ny >> 1, bz * kper, T(0)};
     double acc[1] = {0.0};
-    march<T, BX>(L, kper, op, acc);
+    march<T, BX>(L, kper, xcd, op, acc);
 }
 
 template <class T, int BX>
 __global__ void __launch_bounds__(kBlock) m_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
-                                                         const T* __restrict__ e, T wc, T* __restrict__ y, int kper, T omega)
+                                                         const T* __restrict__ e, T wc, T* __restrict__ y, int kper, int xcd,
+                                                         T omega)
 {
     OpProlongBlack<T> op{f, L.invd, x, e, y, wc, omega, L.nx >> 1, L.ny >> 1};
     double acc[1] = {0.0};
-    march<T, BX>(L, kper, op, acc);
+    march<T, BX>(L, kper, xcd, op, acc);
 }
 
 template <class T, int BX, class TZ, bool BETA>
 __global__ void __launch_bounds__(kBlock) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
-                                                     Coefs beta, Coefs mean, int use_mean, int kper, Reduce R)
+                                                     Coefs beta, Coefs mean, int use_mean, int kper, int xcd, Reduce R)
 {
     OpDir<T, TZ, BETA> op{z, dold, r, dnew, q, BETA ? (T)beta.get() : T(0), use_mean ? (T)mean.get() : T(0)};
     double acc[2] = {0.0, 0.0};
-    march<T, BX>(L, kper, op, acc);
+    march<T, BX>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 
 template <int BX>
 __global__ void __launch_bounds__(kBlock) m_true_residual(LevelView<double> L, const double* __restrict__ f,
-                                                         const double* __restrict__ x, double* __restrict__ r, int kper, Reduce R)
+                                                         const double* __restrict__ x, double* __restrict__ r, int kper, int xcd,
+                                                         Reduce R)
 {
     OpResidual<double> op{f, x, r};
     double acc[2] = {0.0, 0.0};
-    march<double, BX>(L, kper, op, acc);
+    march<double, BX>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 

@@ -31,6 +31,7 @@
 // one-thread-per-column kernels of pp_kernels.hpp, kept as a reference form).
 #include "pp_kernels.hpp"
 #include "pp_march.hpp"
+#include "pp_tail.hpp"
 #include "../../include/pp.h"
 
 #include <algorithm>
@@ -191,6 +192,8 @@ struct Hier {
 
 struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 3, coarse_sweeps = 16;
+    int kit2 = 0;               // K-cycle steps on levels >= 2 (0: kit)
+    int nuv = 0;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
     bool tail = true;           // run the small coarse V-levels in one launch
     double wc = 2.0;
     bool graphs = true;
@@ -198,7 +201,8 @@ struct Params {
     bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
     bool march = true;          // plane-marching stencil kernels (else one thread per cell column)
     int mbx = 64;               // widest march tile in x
-    int mblocks = 1024;         // blocks of a march launch (at most; z split to reach it)
+    int mblocks = 768;          // blocks of a march launch (at most; z split to reach it)
+    int xcd = 2;                // XCD-aware tile order: 0 never, 1 always, 2 below the finest level
 };
 
 struct Handle {
@@ -468,13 +472,14 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         auto make_tail = [&](auto& Hh) {
             Hh.tail = -1;
             if (!prm.tail || nl < 2) return;
-            // levels that fit: small enough, x-pairs above the last level, all iterates in LDS
+            // levels that fit: the first at most kTailMaxCells with even nx, the later
+            // ones (iterates and operators in LDS) at most kTailSmallCells together
             int t = nl - 1;
-            size_t cells = Hh.L[t].n;
+            size_t later = 0;
             while (t - 1 >= 1 && !Hh.L[t - 1].kcyc && Hh.L[t - 1].n <= (size_t)kTailMaxCells &&
-                   (Hh.L[t - 1].nx % 2) == 0 && cells + Hh.L[t - 1].n <= (size_t)kTailLdsCells) {
+                   (Hh.L[t - 1].nx % 2) == 0 && later + Hh.L[t].n <= (size_t)kTailSmallCells) {
+                later += Hh.L[t].n;
                 --t;
-                cells += Hh.L[t].n;
             }
             if (t == nl - 1 || t <= prm.kmax || nl - t > kTailMaxLev) return;  // need at least two levels
             Hh.tail = t;
@@ -488,13 +493,13 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
                 D.L[l - t].c = V.c;
                 D.L[l - t].n = (int)V.n;
                 D.L[l - t].off = off;
-                off += (int)V.n;
+                if (l > t) off += (int)V.n;
             }
             D.Minv = Hh.Minv;
             D.nd = Hh.nd;
             D.wc = prm.wc;
             D.omega = prm.omega;
-            D.nu = prm.nuc;
+            D.nu = prm.nuv > 0 ? prm.nuv : prm.nuc;
             D.coarse_sweeps = prm.coarse_sweeps;
         };
         if (fp64) make_tail(h64);
@@ -561,6 +566,14 @@ static void write_slots(Handle* H, int first, const double* v, int count)
 template <class T>
 static int kid(int id) { return id + (sizeof(T) == 4 ? 0 : 32); }
 
+// XCD-aware tile order for a march launch on a level of this size (see tile_of_block).
+template <class T>
+static int xcd_of(const Handle* H, const LevelView<T>& v)
+{
+    const size_t n = (size_t)v.nx * v.ny * v.nz;
+    return H->prm.xcd == 1 || (H->prm.xcd == 2 && n < ((size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz));
+}
+
 // Launchers: the plane-march kernels, or the per-column kernels when the march is off.
 
 template <class T>
@@ -570,7 +583,7 @@ static void launch_first(Handle* H, const LevelView<T>& v, const T* f, T* x)
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
         with_bx(g.bx, [&](auto B) {
-            m_smooth_first<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, g.kper, om);
+            m_smooth_first<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, g.kper, xcd_of(H, v), om);
         });
     } else {
         const Geo g = geo(v.nx, v.ny, v.nz);
@@ -588,7 +601,8 @@ static dim3 launch_half(Handle* H, const LevelView<T>& v, const T* f, T* x, int 
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
         with_bx(g.bx, [&](auto B) {
-            m_smooth_half<T, decltype(B)::value, NDOT, TQ><<<g.grid, g.block, 0, H->stream>>>(v, f, x, colour, g.kper, q, R, om);
+            m_smooth_half<T, decltype(B)::value, NDOT, TQ><<<g.grid, g.block, 0, H->stream>>>(v, f, x, colour, g.kper, xcd_of(H, v), q, R,
+                                                                                                 om);
         });
         check_launch();
         return g.grid;
@@ -605,7 +619,7 @@ static void launch_restrict(Handle* H, const LevelView<T>& v, const T* f, const 
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, std::min(H->prm.mbx, 32), true, H->prm.mblocks);
         with_bx_le32(g.bx, [&](auto B) {
-            m_residual_restrict<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper);
+            m_residual_restrict<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper, xcd_of(H, v));
         });
     } else {
         const Geo g = geo(v.nx / 2, v.ny / 2, v.nz / 2);
@@ -621,7 +635,7 @@ static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, c
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
         with_bx(g.bx, [&](auto B) {
-            m_prolong_black<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, e, wc, y, g.kper, om);
+            m_prolong_black<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, e, wc, y, g.kper, xcd_of(H, v), om);
         });
     } else {
         const Geo g = geo(v.nx, v.ny, v.nz);
@@ -639,9 +653,11 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
         with_bx(g.bx, [&](auto B) {
             constexpr int BX = decltype(B)::value;
             if (use_beta)
-                m_dir_apply<T, BX, TZ, true><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper, R);
+                m_dir_apply<T, BX, TZ, true><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper,
+                                                                                 xcd_of(H, v), R);
             else
-                m_dir_apply<T, BX, TZ, false><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper, R);
+                m_dir_apply<T, BX, TZ, false><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper,
+                                                                                  xcd_of(H, v), R);
         });
         check_launch();
         return g.grid;
@@ -708,7 +724,7 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         }
         return V.c;
     }
-    const int nu = fine ? H->prm.nu0 : H->prm.nuc;
+    const int nu = fine ? H->prm.nu0 : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0) ? H->prm.nuv : H->prm.nuc;
     {
         // reads f, three face arrays and 1/D; writes x
         TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 6.0);
@@ -774,7 +790,7 @@ template <class T>
 static T* kcycle(Handle* H, Hier<T>& Hh, int l)
 {
     Lev<T>& V = Hh.L[l];
-    const int kit = H->prm.kit;
+    const int kit = (l >= 2 && H->prm.kit2 > 0) ? H->prm.kit2 : H->prm.kit;
     V.d = V.d_a;
     V.d2 = V.d_b;
     for (int it = 0; it < kit; ++it) {
@@ -804,8 +820,8 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
         const Reduce R = red(H, dq_cur, lslot(0, S_DR));
         dim3 grid;
         {
-            // reads z, d_old, three float64 face arrays and r; writes d and q
-            TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 64.0 : 56.0)));
+            // reads z, (d_old,) three float64 face arrays and r; writes d and q
+            TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 56.0 : 48.0)));
             grid = launch_dir<double, P>(H, v, z, H->d, H->d2, H->q64, H->r64, coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
                                          coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1, R);
         }
@@ -968,7 +984,7 @@ static double true_residual(Handle* H, const double* x)
         if (H->prm.march) {
             const MGeo g = mgeo(cfg.nx, cfg.ny, cfg.nz, H->prm.mbx, false, H->prm.mblocks);
             with_bx(g.bx, [&](auto B) {
-                m_true_residual<decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, R);
+                m_true_residual<decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, xcd_of(H, v), R);
             });
         } else {
             const Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
@@ -1073,7 +1089,11 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
     if (const char* s = getenv("PP_TAIL")) p.tail = atoi(s) != 0;
+    if (const char* s = getenv("PP_OMEGA")) p.omega = atof(s);
+    if (const char* s = getenv("PP_KIT2")) p.kit2 = std::max(0, atoi(s));
+    if (const char* s = getenv("PP_NUV")) p.nuv = std::max(0, atoi(s));
     if (const char* s = getenv("PP_MARCH")) p.march = atoi(s) != 0;
+    if (const char* s = getenv("PP_XCD")) p.xcd = atoi(s);
     if (const char* s = getenv("PP_MBLOCKS")) p.mblocks = std::max(64, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBX")) {
         const int b = atoi(s);
