@@ -12,9 +12,12 @@ Prints one JSON line (rank 0).  Only one GPU is supported.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -25,6 +28,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-10 residual & cells·iters/s (HBM GB/s %peak); FP32-refined vs FP64; p50/p99"
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def csrc_sha256():
+    """Hash of the kernel and launch sources (the HBM-traffic profile is valid for these only)."""
+    h = hashlib.sha256()
+    d = os.path.join(HERE, "paper_2104_01636_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(d, "*.hpp")) + glob.glob(os.path.join(d, "*.hip"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter profile of `workload`, or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(HERE, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        m = re.search(r"kernel: (\S+)\s+traffic_bytes_per_launch: (\d+)\s+source_sha256: ([0-9a-f]+)", fh.read())
+    if not m or m.group(1) != kernel or m.group(3) != csrc_sha256():
+        return None
+    return int(m.group(2))
 
 
 def pct(a, q):
@@ -192,7 +219,8 @@ def main():
                 "timing": ("HIP events on the solver's stream around each launch, during the timed steps"
                            if args.kernel_timing == "timed" else
                            "HIP events on the solver's stream around each launch, 2 extra steps after the timed ones"),
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(name, args.workload),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(launches),
                 "algorithmic_bytes_per_launch": int(bytes_ / launches)}
         kern_tab = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": int(v[1]),

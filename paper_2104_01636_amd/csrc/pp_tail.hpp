@@ -114,6 +114,51 @@ struct TailS {
     __device__ T x(int c) const { return xs[c]; }
 };
 
+// Everything one relaxation of cell c reads, gathered before any of it is used.
+template <class T>
+struct TailIn {
+    T ww, we, ws, wn, wb, wt;  // face weights (zero where there is no neighbour)
+    T xw, xe, xs, xn, xb, xt;  // neighbour values
+    T f, invd, xc;
+};
+
+template <class T, class A>
+__device__ inline TailIn<T> tail_gather(const A& a, int c, int fl)
+{
+    const int sy = a.nx, sz = a.nx * a.ny, wrap = (a.nz - 1) * sz;
+    const int cw = (fl & NB_W) ? c - 1 : c, ce = (fl & NB_E) ? c + 1 : c;
+    const int cs = (fl & NB_S) ? c - sy : c, cn = (fl & NB_N) ? c + sy : c;
+    const int cb = (fl & NB_ZLO) ? c + wrap : c - sz, ct = (fl & NB_ZHI) ? c - wrap : c + sz;
+    TailIn<T> v;
+    v.ww = a.wx(cw);
+    v.ws = a.wy(cs);
+    v.we = a.wx(c);
+    v.wn = a.wy(c);
+    v.wb = a.wz(cb);
+    v.wt = a.wz(c);
+    v.f = a.f(c);
+    v.invd = a.invd(c);
+    v.xw = a.x(cw);
+    v.xe = a.x(ce);
+    v.xs = a.x(cs);
+    v.xn = a.x(cn);
+    v.xb = a.x(cb);
+    v.xt = a.x(ct);
+    v.xc = a.x(c);
+    if (!(fl & NB_W)) v.ww = T(0);
+    if (!(fl & NB_S)) v.ws = T(0);
+    return v;
+}
+
+template <class T>
+__device__ inline T tail_update(const TailIn<T>& v, T omega)
+{
+    const T s = v.ww * v.xw + v.we * v.xe + v.ws * v.xs + v.wn * v.xn + v.wb * v.xb + v.wt * v.xt;
+    T xv = (s + v.f) * v.invd;
+    if (omega != T(1)) xv = v.xc + omega * (xv - v.xc);
+    return xv;
+}
+
 template <class T, class A>
 __device__ inline void tail_relax(const A& a, int c, int fl, T omega)
 {
@@ -157,14 +202,29 @@ __device__ inline void pair_cell(int pk, int colour, int& c, int& fl)
     fl = odd ? ((f0 & ~(NB_W | NB_E)) | NB_W | ((f0 & 128) ? 0 : NB_E)) : ((f0 & ~NB_E) | NB_E);
 }
 
+// Half-sweep of the first level: kTailBatch pairs per thread and round (4 in
+// float32, 2 in float64, as registers allow), all loads of their cells issued
+// before any is computed (the cells of one colour are independent).
 template <class T>
 __device__ inline void tail_half_first(const TailG<T>& a, const int* pinfo, int np, int colour, T omega)
 {
-#pragma unroll 2
-    for (int t = threadIdx.x; t < np; t += kTailThreads) {
-        int c, fl;
-        pair_cell(pinfo[t], colour, c, fl);
-        tail_relax<T>(a, c, fl, omega);
+    constexpr int kTailBatch = sizeof(T) == 4 ? 4 : 2;
+    for (int t = threadIdx.x; t < np; t += kTailBatch * kTailThreads) {
+        int c[kTailBatch], fl[kTailBatch];
+        TailIn<T> v[kTailBatch];
+#pragma unroll
+        for (int b = 0; b < kTailBatch; ++b) {
+            const int tb = t + b * kTailThreads;
+            pair_cell(pinfo[tb < np ? tb : t], colour, c[b], fl[b]);
+            v[b] = tail_gather<T>(a, c[b], fl[b]);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep all loads ahead of the arithmetic
+        T x[kTailBatch];
+#pragma unroll
+        for (int b = 0; b < kTailBatch; ++b) x[b] = tail_update(v[b], omega);
+#pragma unroll
+        for (int b = 0; b < kTailBatch; ++b)
+            if (t + b * kTailThreads < np) a.xs[c[b]] = x[b];
     }
     __syncthreads();
 }
@@ -257,8 +317,10 @@ __device__ inline void tail_prolong_small(const TailS<T>& a, const T* e, T wc)
 
 // One V-cycle over the levels of D from a zero guess at the top; the result is
 // left in D.L[0].c.
+// (one block of 16 wavefronts: 4 per SIMD is all the occupancy there is, so the
+// compiler may spend registers on keeping loads in flight)
 template <class T>
-__global__ void __launch_bounds__(kTailThreads) k_tail_vcycle(TailDesc<T> D)
+__global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) k_tail_vcycle(TailDesc<T> D)
 {
     __shared__ T x0[kTailMaxCells];
     __shared__ T sxs[kTailSmallCells], swx[kTailSmallCells], swy[kTailSmallCells], swz[kTailSmallCells],
