@@ -415,9 +415,14 @@ int ppref_solve(int nx, int ny, int nz, double h, const double* rho, const doubl
             double rz = 0.0;
 #pragma omp parallel for reduction(+ : rz) schedule(static)
             for (long c = 0; c < n; ++c) { z[c] = L0->x[c] - mz; rz += r[c] * z[c]; }
-            double beta = inner ? rz / rz_old : 0.0;
+            if (inner) {
+                double beta = rz / rz_old;
 #pragma omp parallel for schedule(static)
-            for (long c = 0; c < n; ++c) d[c] = z[c] + beta * d[c];
+                for (long c = 0; c < n; ++c) d[c] = z[c] + beta * d[c];
+            } else { /* first direction of a (re)start: d = z (d holds no earlier direction) */
+#pragma omp parallel for schedule(static)
+                for (long c = 0; c < n; ++c) d[c] = z[c];
+            }
             k_apply(L0, d, q);
             double dq = 0.0;
 #pragma omp parallel for reduction(+ : dq) schedule(static)
