@@ -42,6 +42,7 @@ struct LevelView {
     const T* wy;
     const T* wz;    // +z face weight (the last plane's face joins plane 0)
     const T* invd;  // 1 / D_c
+    const T* rho = nullptr;  // finest level: density, from which the plane-marching kernels derive the weights
 };
 
 // Reduction target: per-block partials and the output slots.  A reducing

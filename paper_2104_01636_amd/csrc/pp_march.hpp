@@ -15,10 +15,10 @@
 // One barrier per plane: a thread writes LDS buffer (k - k0) & 1, and a buffer
 // is written again only two planes later, after every thread has passed the
 // barrier that follows its last read of it.  The barrier waits for LDS only
-// (not for the global loads in flight), and the global loads of plane k+1 are
-// issued before the barrier of plane k into the other of two register sets,
-// so a wavefront keeps one plane of loads outstanding while it works on the
-// current one.
+// (not for the global loads in flight), and the global loads of plane
+// k + kMarchSets - 1 are issued before the barrier of plane k into a rotating
+// set of registers, so a wavefront keeps kMarchSets - 1 planes of loads
+// outstanding while it works on the current one.
 #pragma once
 #include "pp_kernels.hpp"
 
@@ -64,16 +64,30 @@ __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_b
 // outside the grid) so that apply may use wavefront shuffles.  val at a
 // neighbour must not be changed by the pass itself (the callers write other
 // arrays, or only cells of the colour that val is not read at).
+// Register sets of plane loads (loads are issued kMarchSets - 1 planes ahead
+// of the plane being computed).
+constexpr int kMarchSets = 2;
+
 // Global inputs of one plane k of the tile: own face weights, apply's extras,
 // the halo neighbour values (raw) and halo weights, and the raw inputs at k+1.
 template <class T, class Raw, class Ex>
 struct PlaneRegs {
-    T wx, wy, wz, wxh, wyh;
+    T wx, wy, wz, wxh, wyh;  // weights from memory; with the density: rho, -, rho at k+1, halo rho x, halo rho y
     Raw rx, ry, rn;
     Ex ex;
 };
 
-template <class T, int BX, class Op, class Acc>
+// Face weight beta_f = 2 / (rho_L + rho_R) of the finest level (symmetric in
+// L and R).  Float64: the IEEE division of the set-up, bit for bit; float32
+// (preconditioner only): the hardware reciprocal.
+__device__ inline double face_beta(double a, double b) { return 2.0 / (a + b); }
+__device__ inline float face_beta(float a, float b) { return 2.0f * __builtin_amdgcn_rcpf(a + b); }
+
+// RHO: the level is the finest and its face weights are formed from L.rho
+// (the x and y weights of a cell from the LDS copy of the plane's density,
+// the z weight from the density of the next plane) instead of read from
+// L.wx, L.wy, L.wz: 8 bytes per cell in float64 instead of 24.
+template <class T, int BX, bool RHO, class Op, class Acc>
 __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, Acc& acc)
 {
     using Raw = typename Op::Raw;
@@ -106,63 +120,105 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
 
     auto fetch = [&](Regs& S, int k, int c) {
         const int kt = k < L.nz - 1 ? k + 1 : 0;
-        S.wx = L.wx[c];
-        S.wy = L.wy[c];
-        S.wz = L.wz[c];
+        if constexpr (RHO) {
+            S.wx = L.rho[c];
+            S.wy = T(0);
+            S.wz = L.rho[c + (kt - k) * sz];
+            S.wxh = L.rho[c + oi];
+            S.wyh = L.rho[c + oj * sy];
+        } else {
+            S.wx = L.wx[c];
+            S.wy = L.wy[c];
+            S.wz = L.wz[c];
+            S.wxh = L.wx[c + owx];
+            S.wyh = L.wy[c + owy];
+        }
         S.ex = op.extra(c);
         S.rn = op.load(c + (kt - k) * sz, ic, jc, kt);
         S.rx = op.load(c + oi, ic + oi, jc, k);
         S.ry = op.load(c + oj * sy, ic, jc + oj, k);
-        S.wxh = L.wx[c + owx];
-        S.wyh = L.wy[c + owy];
     };
 
     // prologue: value at k0-1, value and raw inputs at k0, registers of plane k0
     const int kb0 = k0 > 0 ? k0 - 1 : L.nz - 1;
     int c = cell(L.nx, L.ny, ic, jc, k0);
     const T vm0 = op.val(op.load(c + (kb0 - k0) * sz, ic, jc, kb0));
-    T wzb = L.wz[c + (kb0 - k0) * sz];
+    T wzb;
+    if constexpr (RHO) wzb = face_beta(L.rho[c + (kb0 - k0) * sz], L.rho[c]);
+    else wzb = L.wz[c + (kb0 - k0) * sz];
     Raw rc = op.load(c, ic, jc, k0);
-    Regs A, B;
-    fetch(A, k0, c);
+    // kMarchSets register sets: plane k is in set (k - k0) mod kMarchSets and the
+    // loads of plane k + kMarchSets - 1 are issued while plane k is computed
+    Regs R[kMarchSets];
+#pragma unroll
+    for (int s = 0; s < kMarchSets - 1; ++s) {
+        const bool in = k0 + s < k1;
+        fetch(R[s], in ? k0 + s : k0, in ? c + s * sz : c);
+    }
     T vm = act ? vm0 : T(0);
     T vc = act ? op.val(rc) : T(0);
 
-    // One plane: S holds plane k, N receives plane k+1 (plane k again on the
-    // block's last plane, unused).
+    // One plane: S holds plane k, N receives plane k + kMarchSets - 1 (plane k
+    // again near the block's last plane, unused).
     auto step = [&](Regs& S, Regs& N, int k, int c, int buf) {
-        const bool more = k + 1 < k1;
-        fetch(N, more ? k + 1 : k, more ? c + sz : c);
+        constexpr int ahead = kMarchSets - 1;
+        const bool more = k + ahead < k1;
+        fetch(N, more ? k + ahead : k, more ? c + ahead * sz : c);
         const T vp = act ? op.val(S.rn) : T(0);
         const T vxh = hx ? op.val(S.rx) : T(0);
         const T vyh = hy ? op.val(S.ry) : T(0);
         sv[buf][ty][tx] = vc;
-        swx[buf][ty][tx] = act ? S.wx : T(0);
-        swy[buf][ty][tx] = act ? S.wy : T(0);
+        if constexpr (RHO) {
+            swx[buf][ty][tx] = act ? S.wx : T(1);
+        } else {
+            swx[buf][ty][tx] = act ? S.wx : T(0);
+            swy[buf][ty][tx] = act ? S.wy : T(0);
+        }
         lds_barrier();
         const T vw = tx > 0 ? sv[buf][ty][tx - 1] : vxh;
         const T ve = tx < BX - 1 ? (in_e ? sv[buf][ty][tx + 1] : T(0)) : vxh;
         const T vs = ty > 0 ? sv[buf][ty - 1][tx] : vyh;
         const T vn = ty < BY - 1 ? (in_n ? sv[buf][ty + 1][tx] : T(0)) : vyh;
-        const T ww = i > 0 ? (tx > 0 ? swx[buf][ty][tx - 1] : S.wxh) : T(0);
-        const T ws = j > 0 ? (ty > 0 ? swy[buf][ty - 1][tx] : S.wyh) : T(0);
+        T ww, we, ws, wn, wt;
+        if constexpr (RHO) {
+            // neighbour densities: LDS inside the tile, the halo value on its edge
+            const T rc = S.wx;
+            const T rw = tx > 0 ? swx[buf][ty][tx - 1] : S.wxh;
+            const T re = tx < BX - 1 ? swx[buf][ty][tx + 1] : S.wxh;
+            const T rs = ty > 0 ? swx[buf][ty - 1][tx] : S.wyh;
+            const T rn = ty < BY - 1 ? swx[buf][ty + 1][tx] : S.wyh;
+            ww = i > 0 ? face_beta(rw, rc) : T(0);
+            we = in_e ? face_beta(rc, re) : T(0);
+            ws = j > 0 ? face_beta(rs, rc) : T(0);
+            wn = in_n ? face_beta(rc, rn) : T(0);
+            wt = face_beta(rc, S.wz);
+        } else {
+            ww = i > 0 ? (tx > 0 ? swx[buf][ty][tx - 1] : S.wxh) : T(0);
+            ws = j > 0 ? (ty > 0 ? swy[buf][ty - 1][tx] : S.wyh) : T(0);
+            we = S.wx;
+            wn = S.wy;
+            wt = S.wz;
+        }
         Stencil<T> st;
-        st.s = ww * vw + S.wx * ve + ws * vs + S.wy * vn + wzb * vm + S.wz * vp;
-        st.d = ww + S.wx + ws + S.wy + wzb + S.wz;
+        st.s = ww * vw + we * ve + ws * vs + wn * vn + wzb * vm + wt * vp;
+        st.d = ww + we + ws + wn + wzb + wt;
         op.apply(c, i, j, k, vc, rc, S.ex, st, acc, act);
         vm = vc;
         vc = vp;
         rc = S.rn;
-        wzb = S.wz;
+        wzb = wt;
     };
 
-    // two planes per trip so that the register sets alternate without copies
+    // kMarchSets planes per trip so that the register sets rotate without copies
     int k = k0;
-    for (; k + 1 < k1; k += 2, c += 2 * sz) {
-        step(A, B, k, c, 0);
-        step(B, A, k + 1, c + sz, 1);
+    for (; k + kMarchSets - 1 < k1; k += kMarchSets, c += kMarchSets * sz) {
+#pragma unroll
+        for (int s = 0; s < kMarchSets; ++s)
+            step(R[s], R[(s + kMarchSets - 1) % kMarchSets], k + s, c + s * sz, (k + s - k0) & 1);
     }
-    if (k < k1) step(A, B, k, c, 0);
+#pragma unroll
+    for (int s = 0; s < kMarchSets - 1; ++s)
+        if (k + s < k1) step(R[s], R[(s + kMarchSets - 1) % kMarchSets], k + s, c + s * sz, (k + s - k0) & 1);
 }
 
 // ---------------------------------------------------------------- operations
@@ -312,26 +368,26 @@ struct OpRestrict {
 
 // ---------------------------------------------------------------- kernels
 
-template <class T, int BX>
+template <class T, int BX, bool RHO>
 __global__ void __launch_bounds__(kBlock) m_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
                                                         int xcd, T omega)
 {
     OpFirst<T> op{f, L.invd, x, omega};
     double acc[1] = {0.0};
-    march<T, BX>(L, kper, xcd, op, acc);
+    march<T, BX, RHO>(L, kper, xcd, op, acc);
 }
 
-template <class T, int BX, int NDOT, class TQ>
+template <class T, int BX, bool RHO, int NDOT, class TQ>
 __global__ void __launch_bounds__(kBlock) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
                                                        int xcd, const TQ* __restrict__ q, Reduce R, T omega)
 {
     OpHalf<T, NDOT, TQ> op{f, L.invd, x, q, colour, omega};
     double acc[NDOT > 0 ? NDOT : 1] = {};
-    march<T, BX>(L, kper, xcd, op, acc);
+    march<T, BX, RHO>(L, kper, xcd, op, acc);
     if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
 }
 
-template <class T, int BX>
+template <class T, int BX, bool RHO>
 __global__ void __launch_bounds__(kBlock) m_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                              T* __restrict__ rc, int kper, int xcd)
 {
@@ -340,38 +396,38 @@ __global__ void __launch_bounds__(kBlock) m_residual_restrict(LevelView<T> L, co
     tile_of_block(bx, by, bz, xcd);
     OpRestrict<T, BX> op{f, x, rc, L.nx >> 1, L.ny >> 1, bz * kper, T(0)};
     double acc[1] = {0.0};
-    march<T, BX>(L, kper, xcd, op, acc);
+    march<T, BX, RHO>(L, kper, xcd, op, acc);
 }
 
-template <class T, int BX>
+template <class T, int BX, bool RHO>
 __global__ void __launch_bounds__(kBlock) m_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                          const T* __restrict__ e, T wc, T* __restrict__ y, int kper, int xcd,
                                                          T omega)
 {
     OpProlongBlack<T> op{f, L.invd, x, e, y, wc, omega, L.nx >> 1, L.ny >> 1};
     double acc[1] = {0.0};
-    march<T, BX>(L, kper, xcd, op, acc);
+    march<T, BX, RHO>(L, kper, xcd, op, acc);
 }
 
-template <class T, int BX, class TZ, bool BETA>
+template <class T, int BX, bool RHO, class TZ, bool BETA>
 __global__ void __launch_bounds__(kBlock) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
                                                      Coefs beta, Coefs mean, int use_mean, int kper, int xcd, Reduce R)
 {
     OpDir<T, TZ, BETA> op{z, dold, r, dnew, q, BETA ? (T)beta.get() : T(0), use_mean ? (T)mean.get() : T(0)};
     double acc[2] = {0.0, 0.0};
-    march<T, BX>(L, kper, xcd, op, acc);
+    march<T, BX, RHO>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 
-template <int BX>
+template <int BX, bool RHO>
 __global__ void __launch_bounds__(kBlock) m_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                          const double* __restrict__ x, double* __restrict__ r, int kper, int xcd,
                                                          Reduce R)
 {
     OpResidual<double> op{f, x, r};
     double acc[2] = {0.0, 0.0};
-    march<double, BX>(L, kper, xcd, op, acc);
+    march<double, BX, RHO>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 

@@ -203,6 +203,7 @@ struct Params {
     int mbx = 64;               // widest march tile in x
     int mblocks = 768;          // blocks of a march launch (at most; z split to reach it)
     int xcd = 2;                // XCD-aware tile order: 0 never, 1 always, 2 below the finest level
+    bool rho = true;            // finest-level march kernels form the weights from the density
 };
 
 struct Handle {
@@ -236,6 +237,8 @@ struct Handle {
     double *f64 = nullptr, *r64 = nullptr, *x64 = nullptr, *q64 = nullptr;
     double *d = nullptr, *d2 = nullptr, *d_a = nullptr, *d_b = nullptr;
     float* r32 = nullptr;
+    double* rho64 = nullptr;   // copy of the density (finest-level weights of the plane-marching kernels)
+    float* rho32 = nullptr;    // its float32 copy (float32 preconditioner)
     // captured Krylov steps: [0] first step, [1] odd steps, [2] even steps >= 2
     hipGraphExec_t kexec[3] = {nullptr, nullptr, nullptr};
 
@@ -424,6 +427,8 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     double* d_a = P.take<double>(n0);
     double* d_b = P.take<double>(n0);
     float* r32 = fp64 ? nullptr : P.take<float>(n0);
+    double* rho64 = P.take<double>(n0);
+    float* rho32 = fp64 ? nullptr : P.take<float>(n0);
 
     auto make_h = [&](auto tag, auto& Hh, bool alloc) {
         using T = decltype(tag);
@@ -462,12 +467,17 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         H->c64 = c64; H->c32 = c32;
         H->dense_work = dense_work; H->M64 = M64; H->M32 = M32;
         H->f64 = f64; H->r64 = r64; H->x64 = x64; H->q64 = q64; H->r32 = r32;
+        H->rho64 = rho64; H->rho32 = rho32;
         H->d = H->d_a = d_a; H->d2 = H->d_b = d_b;
         H->partials = partials; H->slots = slots;
         // operator views
         for (int l = 0; l < nl; ++l) {
             h64.L[l].v = LevelView<double>{nx[l], ny[l], nz[l], c64[l].wx, c64[l].wy, c64[l].wz, c64[l].invd};
             h32.L[l].v = LevelView<float>{nx[l], ny[l], nz[l], c32[l].wx, c32[l].wy, c32[l].wz, c32[l].invd};
+        }
+        if (prm.rho) {
+            h64.L[0].v.rho = rho64;
+            h32.L[0].v.rho = rho32;
         }
         auto make_tail = [&](auto& Hh) {
             Hh.tail = -1;
@@ -566,6 +576,33 @@ static void write_slots(Handle* H, int first, const double* v, int count)
 template <class T>
 static int kid(int id) { return id + (sizeof(T) == 4 ? 0 : 32); }
 
+// The float64 finest-level operator (with the density when the plane-marching
+// kernels derive the weights from it).
+static LevelView<double> fine64(const Handle* H)
+{
+    LevelView<double> v{H->cfg.nx, H->cfg.ny, H->cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
+    if (H->prm.rho) v.rho = H->rho64;
+    return v;
+}
+
+// Arrays a pass reads for the face weights of a level: the density alone when
+// the plane-marching kernels form them from it, else the three weight arrays.
+template <class T>
+static double weight_arrays(const Handle* H, const LevelView<T>& v)
+{
+    return (v.rho && H->prm.march) ? 1.0 : 3.0;
+}
+
+template <bool B>
+using RhoC = std::integral_constant<bool, B>;
+// Calls f(RhoC<true>{}) when the view's weights come from the density.
+template <class T, class F>
+static void with_rho(const LevelView<T>& v, F&& f)
+{
+    if (v.rho) f(RhoC<true>{});
+    else f(RhoC<false>{});
+}
+
 // XCD-aware tile order for a march launch on a level of this size (see tile_of_block).
 template <class T>
 static int xcd_of(const Handle* H, const LevelView<T>& v)
@@ -583,7 +620,10 @@ static void launch_first(Handle* H, const LevelView<T>& v, const T* f, T* x)
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
         with_bx(g.bx, [&](auto B) {
-            m_smooth_first<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, g.kper, xcd_of(H, v), om);
+            with_rho(v, [&](auto R) {
+                m_smooth_first<T, decltype(B)::value, decltype(R)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, g.kper,
+                                                                                                           xcd_of(H, v), om);
+            });
         });
     } else {
         const Geo g = geo(v.nx, v.ny, v.nz);
@@ -601,8 +641,10 @@ static dim3 launch_half(Handle* H, const LevelView<T>& v, const T* f, T* x, int 
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
         with_bx(g.bx, [&](auto B) {
-            m_smooth_half<T, decltype(B)::value, NDOT, TQ><<<g.grid, g.block, 0, H->stream>>>(v, f, x, colour, g.kper, xcd_of(H, v), q, R,
-                                                                                                 om);
+            with_rho(v, [&](auto W) {
+                m_smooth_half<T, decltype(B)::value, decltype(W)::value, NDOT, TQ>
+                    <<<g.grid, g.block, 0, H->stream>>>(v, f, x, colour, g.kper, xcd_of(H, v), q, R, om);
+            });
         });
         check_launch();
         return g.grid;
@@ -619,7 +661,10 @@ static void launch_restrict(Handle* H, const LevelView<T>& v, const T* f, const 
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, std::min(H->prm.mbx, 32), true, H->prm.mblocks);
         with_bx_le32(g.bx, [&](auto B) {
-            m_residual_restrict<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper, xcd_of(H, v));
+            with_rho(v, [&](auto R) {
+                m_residual_restrict<T, decltype(B)::value, decltype(R)::value>
+                    <<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper, xcd_of(H, v));
+            });
         });
     } else {
         const Geo g = geo(v.nx / 2, v.ny / 2, v.nz / 2);
@@ -635,7 +680,10 @@ static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, c
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
         with_bx(g.bx, [&](auto B) {
-            m_prolong_black<T, decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, e, wc, y, g.kper, xcd_of(H, v), om);
+            with_rho(v, [&](auto R) {
+                m_prolong_black<T, decltype(B)::value, decltype(R)::value>
+                    <<<g.grid, g.block, 0, H->stream>>>(v, f, x, e, wc, y, g.kper, xcd_of(H, v), om);
+            });
         });
     } else {
         const Geo g = geo(v.nx, v.ny, v.nz);
@@ -651,13 +699,16 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
         with_bx(g.bx, [&](auto B) {
-            constexpr int BX = decltype(B)::value;
-            if (use_beta)
-                m_dir_apply<T, BX, TZ, true><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper,
-                                                                                 xcd_of(H, v), R);
-            else
-                m_dir_apply<T, BX, TZ, false><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean, use_mean, g.kper,
-                                                                                  xcd_of(H, v), R);
+            with_rho(v, [&](auto W) {
+                constexpr int BX = decltype(B)::value;
+                constexpr bool RHO = decltype(W)::value;
+                if (use_beta)
+                    m_dir_apply<T, BX, RHO, TZ, true><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean,
+                                                                                          use_mean, g.kper, xcd_of(H, v), R);
+                else
+                    m_dir_apply<T, BX, RHO, TZ, false><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean,
+                                                                                           use_mean, g.kper, xcd_of(H, v), R);
+            });
         });
         check_launch();
         return g.grid;
@@ -674,9 +725,9 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
     Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
     dim3 grid;
     {
-        // reads x, f, three face arrays and 1/D; writes one colour (and reads q for the dot)
+        // reads x, f, 1/D and the weights (or the density); writes one colour (and reads q for the dot)
         TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
-                     (double)V.n * (6.5 * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
+                     (double)V.n * ((3.5 + weight_arrays(H, V.v)) * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
         if (ndot == 0) grid = launch_half<T, 0, TQ>(H, V.v, f, x, colour, q, R);
         else if (ndot == 1) grid = launch_half<T, 1, TQ>(H, V.v, f, x, colour, q, R);
         else grid = launch_half<T, 2, TQ>(H, V.v, f, x, colour, q, R);
@@ -709,7 +760,7 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
             // symmetric block of red-black sweeps (also the whole cycle when the
             // finest level cannot be coarsened)
             {
-                TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 6.0);
+                TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
                 launch_first<T>(H, V.v, f, V.c);
             }
             const int ns = H->prm.coarse_sweeps;
@@ -726,8 +777,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     }
     const int nu = fine ? H->prm.nu0 : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0) ? H->prm.nuv : H->prm.nuc;
     {
-        // reads f, three face arrays and 1/D; writes x
-        TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * 6.0);
+        // reads f, 1/D and the weights (or the density); writes x
+        TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
         launch_first<T>(H, V.v, f, V.c);
     }
     for (int s = 1; s < nu; ++s) {
@@ -736,8 +787,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     }
     Lev<T>& C = Hh.L[l + 1];
     {
-        // reads x, f and three face arrays; writes the coarse right-hand side
-        TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (5.0 + 0.125));
+        // reads x, f and the weights (or the density); writes the coarse right-hand side
+        TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (2.125 + weight_arrays(H, V.v)));
         launch_restrict<T>(H, V.v, f, V.c, C.rhs);
     }
     T* e;
@@ -750,8 +801,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         wc = (T)H->prm.wc;
     }
     {
-        // reads x, f, three face arrays, 1/D and the coarse correction; writes y
-        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (7.0 + 0.125));
+        // reads x, f, 1/D, the weights (or the density) and the coarse correction; writes y
+        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (4.125 + weight_arrays(H, V.v)));
         launch_prolong_black<T>(H, V.v, f, V.c, e, wc, V.c2);
     }
     T* cur = V.c2;
@@ -816,12 +867,13 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
     const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
     const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
     {
-        const LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
+        const LevelView<double> v = fine64(H);
         const Reduce R = red(H, dq_cur, lslot(0, S_DR));
         dim3 grid;
         {
-            // reads z, (d_old,) three float64 face arrays and r; writes d and q
-            TimeScope ts(H, kid<double>(KT_DIR_APPLY), (double)n0 * ((double)sizeof(P) + (k > 0 ? 56.0 : 48.0)));
+            // reads z, (d_old,) the float64 weights (or density) and r; writes d and q
+            TimeScope ts(H, kid<double>(KT_DIR_APPLY),
+                         (double)n0 * ((double)sizeof(P) + (k > 0 ? 32.0 : 24.0) + 8.0 * weight_arrays(H, v)));
             grid = launch_dir<double, P>(H, v, z, H->d, H->d2, H->q64, H->r64, coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
                                          coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1, R);
         }
@@ -924,6 +976,12 @@ static void set_density(Handle* H, const double* rho)
     if (H->host_slots[G_RHOBAD] != 0.0)
         throw Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
                                          " entries that are not finite or not > 0");
+    // the handle's own copies of the density (the caller keeps rho)
+    PP_HIP(hipMemcpyAsync(H->rho64, rho, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+    if (H->rho32) {
+        k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->rho64, H->rho32);
+        check_launch();
+    }
     for (int l = 0; l < nl; ++l) {
         Geo g = geo(H->lnx[l], H->lny[l], H->lnz[l]);
         if (l == 0)
@@ -976,15 +1034,18 @@ static double prepare_rhs(Handle* H, const double* rhs)
 static double true_residual(Handle* H, const double* x)
 {
     const pp_config& cfg = H->cfg;
-    const LevelView<double> v{cfg.nx, cfg.ny, cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
+    const LevelView<double> v = fine64(H);
     {
-        // reads f, x and three float64 face arrays; writes r
-        TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * 48.0);
+        // reads f, x and the float64 weights (or density); writes r
+        TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * (24.0 + 8.0 * weight_arrays(H, v)));
         const Reduce R = red(H, G_TRR, G_TRSUM);
         if (H->prm.march) {
             const MGeo g = mgeo(cfg.nx, cfg.ny, cfg.nz, H->prm.mbx, false, H->prm.mblocks);
             with_bx(g.bx, [&](auto B) {
-                m_true_residual<decltype(B)::value><<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, xcd_of(H, v), R);
+                with_rho(v, [&](auto W) {
+                    m_true_residual<decltype(B)::value, decltype(W)::value>
+                        <<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, xcd_of(H, v), R);
+                });
             });
         } else {
             const Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
@@ -1094,6 +1155,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NUV")) p.nuv = std::max(0, atoi(s));
     if (const char* s = getenv("PP_MARCH")) p.march = atoi(s) != 0;
     if (const char* s = getenv("PP_XCD")) p.xcd = atoi(s);
+    if (const char* s = getenv("PP_RHO")) p.rho = atoi(s) != 0;
     if (const char* s = getenv("PP_MBLOCKS")) p.mblocks = std::max(64, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBX")) {
         const int b = atoi(s);
