@@ -261,14 +261,18 @@ __global__ void __launch_bounds__(kBlock) k_prolong_black(LevelView<T> L, const 
 // d_new = (z - m) + b * d_old, q = K d_new; reduces <d_new, q> and <d_new, r>.
 // m = s[msum]/n (mean projection, finest level only) and b from the slots.  The
 // preconditioned residual z may be stored in a lower precision TZ than d and q.
-template <class T, class TZ = T>
+// FINE (the finest level's Krylov step): also applies the previous step's
+// deferred x += ap * d_old (when use_beta, i.e. after the first step).
+template <class T, class TZ = T, bool FINE = false>
 __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
-                                                     Coefs beta, int use_beta, Coefs mean, int use_mean, int kper, Reduce R)
+                                                     T* __restrict__ x, Coefs beta, int use_beta, Coefs mean, int use_mean,
+                                                     Coefs aprev, int kper, Reduce R)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     const T b = use_beta ? (T)beta.get() : T(0);
     const T m = use_mean ? (T)mean.get() : T(0);
+    const T ap = (FINE && use_beta) ? (T)aprev.get() : T(0);
     double acc[2] = {0.0, 0.0};
     if (t.act) {
         auto dv = [&](int c, int, int, int) { return use_beta ? ((T)z[c] - m) + b * dold[c] : ((T)z[c] - m); };
@@ -282,13 +286,16 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* 
             q[c] = qc;
             acc[0] += (double)dc * (double)qc;
             acc[1] += (double)dc * (double)r[c];
+            if constexpr (FINE) {
+                if (use_beta) x[c] = x[c] + ap * dold[c];
+            }
         }
     }
     reduce_finish<2>(acc, R);
 }
 
-// x += a d (or x = a d when first), r -= a q (unless skip_r); reduces ||r||^2 and
-// sum(r); with r32 also writes the float32 copy of r.  n is even (every level
+// x += a d (or x = a d when first; only with do_x), r -= a q (unless skip_r);
+// reduces ||r||^2 and sum(r); with r32 also writes the float32 copy of r.  n is even (every level
 // has an even number of planes): a thread handles pairs of cells with 2-wide
 // loads, two pairs per trip.
 template <class T> struct Vec2;
@@ -298,7 +305,7 @@ template <> struct Vec2<double> { using type = double2; };
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_update_xr(int n, T* __restrict__ x, const T* __restrict__ d, T* __restrict__ r,
                                                      const T* __restrict__ q, Coefs alpha, int first, int skip_r, int want_red,
-                                                     Reduce R, float* __restrict__ r32)
+                                                     Reduce R, float* __restrict__ r32, int do_x)
 {
     using V = typename Vec2<T>::type;
     const T a = (T)alpha.get();
@@ -312,17 +319,19 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(int n, T* __restrict__ x, 
     float2* s2 = reinterpret_cast<float2*>(r32);
 #pragma unroll 2
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
-        const V dv = d2[p];
-        V xv;
-        if (first) {
-            xv.x = a * dv.x;
-            xv.y = a * dv.y;
-        } else {
-            xv = x2[p];
-            xv.x = xv.x + a * dv.x;
-            xv.y = xv.y + a * dv.y;
+        if (do_x) {
+            const V dv = d2[p];
+            V xv;
+            if (first) {
+                xv.x = a * dv.x;
+                xv.y = a * dv.y;
+            } else {
+                xv = x2[p];
+                xv.x = xv.x + a * dv.x;
+                xv.y = xv.y + a * dv.y;
+            }
+            x2[p] = xv;
         }
-        x2[p] = xv;
         if (!skip_r) {
             V rv = r2[p];
             const V qv = q2[p];

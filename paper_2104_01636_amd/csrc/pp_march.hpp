@@ -293,28 +293,34 @@ struct OpProlongBlack {  // y = x + wc P e on red cells; black SOR update from t
     }
 };
 
-template <class T, class TZ, bool BETA>
-struct OpDir {  // d_new = (z - m) + b d_old (d_new = z - m without BETA), q = K d_new; dots <d,q>, <d,r>
+// d_new = (z - m) + b d_old (d_new = z - m without BETA), q = K d_new; dots
+// <d,q> and <d,r>.  FINE (the finest level's Krylov step): with BETA also the
+// previous step's deferred x += ap * d_old.
+template <class T, class TZ, bool BETA, bool FINE>
+struct OpDir {
     const TZ* z;
     const T* dold;
     const T* r;
     T* dnew;
     T* q;
-    T b, m;
+    T* x;
+    T b, m, ap;
     struct Raw { TZ z; T d; };
-    using Ex = T;
+    struct Ex { T r, x; };
     __device__ Raw load(int c, int, int, int) const { return {z[c], BETA ? dold[c] : T(0)}; }
     __device__ T val(const Raw& a) const { return BETA ? ((T)a.z - m) + b * a.d : ((T)a.z - m); }
-    __device__ Ex extra(int c) const { return r[c]; }
+    __device__ Ex extra(int c) const { return {r[c], (FINE && BETA) ? x[c] : T(0)}; }
     template <class A>
-    __device__ void apply(int c, int, int, int, T vc, const Raw&, Ex rv, const Stencil<T>& st, A& acc, bool act) const
+    __device__ void apply(int c, int, int, int, T vc, const Raw& own, const Ex& ev, const Stencil<T>& st, A& acc,
+                          bool act) const
     {
         if (!act) return;
         const T qc = st.d * vc - st.s;
         dnew[c] = vc;
         q[c] = qc;
         acc[0] += (double)vc * (double)qc;
-        acc[1] += (double)vc * (double)rv;
+        acc[1] += (double)vc * (double)ev.r;
+        if constexpr (FINE && BETA) x[c] = ev.x + ap * own.d;
     }
 };
 
@@ -409,12 +415,14 @@ __global__ void __launch_bounds__(kBlock) m_prolong_black(LevelView<T> L, const 
     march<T, BX, RHO>(L, kper, xcd, op, acc);
 }
 
-template <class T, int BX, bool RHO, class TZ, bool BETA>
+template <class T, int BX, bool RHO, class TZ, bool BETA, bool FINE>
 __global__ void __launch_bounds__(kBlock) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
-                                                     Coefs beta, Coefs mean, int use_mean, int kper, int xcd, Reduce R)
+                                                     T* __restrict__ x, Coefs beta, Coefs mean, int use_mean, Coefs aprev,
+                                                     int kper, int xcd, Reduce R)
 {
-    OpDir<T, TZ, BETA> op{z, dold, r, dnew, q, BETA ? (T)beta.get() : T(0), use_mean ? (T)mean.get() : T(0)};
+    OpDir<T, TZ, BETA, FINE> op{z, dold, r, dnew, q, x, BETA ? (T)beta.get() : T(0), use_mean ? (T)mean.get() : T(0),
+                                (FINE && BETA) ? (T)aprev.get() : T(0)};
     double acc[2] = {0.0, 0.0};
     march<T, BX, RHO>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);

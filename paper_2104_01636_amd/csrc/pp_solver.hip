@@ -692,9 +692,10 @@ static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, c
     check_launch();
 }
 
-template <class T, class TZ>
-static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* dold, T* dnew, T* q, const T* r, Coefs beta,
-                       int use_beta, Coefs mean, int use_mean, const Reduce& R)
+// FINE: the finest level's step (dot <d,q> only; x += aprev * d_old after the first step).
+template <class T, class TZ, bool FINE = false>
+static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* dold, T* dnew, T* q, const T* r, T* x,
+                       Coefs beta, int use_beta, Coefs mean, int use_mean, Coefs aprev, const Reduce& R)
 {
     if (H->prm.march) {
         const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
@@ -703,18 +704,19 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
                 constexpr int BX = decltype(B)::value;
                 constexpr bool RHO = decltype(W)::value;
                 if (use_beta)
-                    m_dir_apply<T, BX, RHO, TZ, true><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean,
-                                                                                          use_mean, g.kper, xcd_of(H, v), R);
+                    m_dir_apply<T, BX, RHO, TZ, true, FINE><<<g.grid, g.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, g.kper, xcd_of(H, v), R);
                 else
-                    m_dir_apply<T, BX, RHO, TZ, false><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, mean,
-                                                                                           use_mean, g.kper, xcd_of(H, v), R);
+                    m_dir_apply<T, BX, RHO, TZ, false, FINE><<<g.grid, g.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, g.kper, xcd_of(H, v), R);
             });
         });
         check_launch();
         return g.grid;
     }
     const Geo g = geo(v.nx, v.ny, v.nz);
-    k_dir_apply<T, TZ><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, beta, use_beta, mean, use_mean, g.kper, R);
+    k_dir_apply<T, TZ, FINE><<<g.grid, g.block, 0, H->stream>>>(v, z, dold, dnew, q, r, x, beta, use_beta, mean, use_mean, aprev,
+                                                                g.kper, R);
     check_launch();
     return g.grid;
 }
@@ -821,7 +823,7 @@ static void dir_apply(Handle* H, Lev<T>& V, bool fine, const T* z, int it, int l
     Coefs beta = coef(H, lslot(l, S_ZQ), dq_prev, -1.0);
     Coefs mn = coef(H, lslot(l, S_SUMZ), -1, 1.0 / (double)V.n);
     Reduce R = red(H, dq_cur, lslot(l, S_DR));
-    finish(H, R, launch_dir<T, T>(H, V.v, z, V.d, V.d2, V.q, V.rhs, beta, it > 0, mn, mean, R), 2);
+    finish(H, R, launch_dir<T, T>(H, V.v, z, V.d, V.d2, V.q, V.rhs, (T*)nullptr, beta, it > 0, mn, mean, beta, R), 2);
 }
 
 template <class T>
@@ -831,7 +833,7 @@ static void update_xr(Handle* H, Lev<T>& V, T* x, int it, int l, bool first, boo
     Coefs alpha = coef(H, lslot(l, S_DR), dq_cur, 1.0);
     const Reduce R = red(H, lslot(l, S_RR), lslot(l, S_RSUM));
     k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>((int)V.n, x, V.d2, V.rhs, V.q, alpha, first, skip_r, want, R,
-                                                         (float*)nullptr);
+                                                         (float*)nullptr, 1);
     check_launch();
     if (want) finish(H, R, lin_grid(V.n), 2);
 }
@@ -856,36 +858,43 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l)
 // One step of the finest-level flexible CG, float64 throughout (x, r, d, q and
 // the operator from rho), preconditioned by one multigrid cycle in precision P:
 // z = M r (the cycle also reduces sum(z) and <z, q_old>), d = (z - mean z) +
-// beta d_old, q = K d with <d, q> and <d, r>, then x += alpha d, r -= alpha q
-// (and the float32 copy of r for a float32 cycle) with ||r||^2.
+// beta d_old, q = K d with <d, q> and <d, r>, then r -= alpha q (and the float32
+// copy of r for a float32 cycle) with ||r||^2, alpha = <d, r> / <d, q>.  The x
+// update is deferred: step k applies x += alpha_{k-1} d_{k-1} while it reads
+// d_{k-1} anyway, and fcg() applies the last one.
 template <class P>
 static void krylov_step(Handle* H, Hier<P>& Hh, int k)
 {
     const pp_config& cfg = H->cfg;
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
-    P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, k > 0 ? 2 : 1, H->q64);
     const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
     const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
+    P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, k > 0 ? 2 : 1, H->q64);
     {
         const LevelView<double> v = fine64(H);
+        // alpha of the previous step is read before this launch's totals replace DR
         const Reduce R = red(H, dq_cur, lslot(0, S_DR));
         dim3 grid;
         {
-            // reads z, (d_old,) the float64 weights (or density) and r; writes d and q
+            // reads z, the float64 weights (or density), r and, after the first step, d_old and x;
+            // writes d, q (and x)
             TimeScope ts(H, kid<double>(KT_DIR_APPLY),
-                         (double)n0 * ((double)sizeof(P) + (k > 0 ? 32.0 : 24.0) + 8.0 * weight_arrays(H, v)));
-            grid = launch_dir<double, P>(H, v, z, H->d, H->d2, H->q64, H->r64, coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
-                                         coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1, R);
+                         (double)n0 * ((double)sizeof(P) + (k > 0 ? 48.0 : 24.0) + 8.0 * weight_arrays(H, v)));
+            grid = launch_dir<double, P, true>(H, v, z, H->d, H->d2, H->q64, H->r64, H->x64,
+                                               coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
+                                               coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1,
+                                               coef(H, lslot(0, S_DR), dq_prev, 1.0), R);
         }
         finish(H, R, grid, 2);
     }
     {
         const Reduce R = red(H, lslot(0, S_RR), lslot(0, S_RSUM));
         {
-            // reads x, d, r and q; writes x, r and the float32 copy of r
-            TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (48.0 + (H->r32 ? 4.0 : 0.0)));
+            // reads r and q; writes r and the float32 copy of r
+            TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (24.0 + (H->r32 ? 4.0 : 0.0)));
             k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
-                                                                        coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1, R, H->r32);
+                                                                        coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1, R,
+                                                                        H->r32, 0);
             check_launch();
         }
         finish(H, R, lin_grid(n0), 2);
@@ -955,6 +964,14 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
         rn = std::sqrt(std::max(0.0, H->host_slots[lslot(0, S_RR)]));
         if (!(rn == rn)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
         if (rn <= rnorm_stop) { ++k; break; }
+    }
+    if (k > 0) {  // the deferred x += alpha d of the last step
+        const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
+        const int last = k - 1;
+        const Coefs a = coef(H, lslot(0, S_DR), lslot(0, (last & 1) ? S_DQ1 : S_DQ0), 1.0);
+        k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d, H->r64, H->q64, a, 0, 1, 0,
+                                                                    red(H, G_FN2), (float*)nullptr, 1);
+        check_launch();
     }
     if (rnorm_out) *rnorm_out = rn;
     return k;
@@ -1100,7 +1117,7 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
                 double* z = mgcycle<double, double>(H, H->h64, 0, H->r64, 0, nullptr);
                 k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, z, H->r64, H->q64,
                                                                             coef(H, G_ONE, -1, 1.0), 0, 1, 0,
-                                                                            red(H, G_FN2), (float*)nullptr);
+                                                                            red(H, G_FN2), (float*)nullptr, 1);
                 check_launch();
                 ++iters;
                 continue;
