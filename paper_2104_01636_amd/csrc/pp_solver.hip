@@ -194,6 +194,7 @@ struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 3, coarse_sweeps = 16;
     int kit2 = 0;               // K-cycle steps on levels >= 2 (0: kit)
     int nuv = 0;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
+    int nu1 = 0;                // sweeps on level 1 (0: nuc)
     bool tail = true;           // run the small coarse V-levels in one launch
     double wc = 2.0;
     bool graphs = true;
@@ -777,7 +778,10 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         }
         return V.c;
     }
-    const int nu = fine ? H->prm.nu0 : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0) ? H->prm.nuv : H->prm.nuc;
+    const int nu = fine ? H->prm.nu0
+               : (l == 1 && H->prm.nu1 > 0)                            ? H->prm.nu1
+               : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0)        ? H->prm.nuv
+                                                                       : H->prm.nuc;
     {
         // reads f, 1/D and the weights (or the density); writes x
         TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
@@ -1170,6 +1174,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_OMEGA")) p.omega = atof(s);
     if (const char* s = getenv("PP_KIT2")) p.kit2 = std::max(0, atoi(s));
     if (const char* s = getenv("PP_NUV")) p.nuv = std::max(0, atoi(s));
+    if (const char* s = getenv("PP_NU1")) p.nu1 = std::max(0, atoi(s));
     if (const char* s = getenv("PP_MARCH")) p.march = atoi(s) != 0;
     if (const char* s = getenv("PP_XCD")) p.xcd = atoi(s);
     if (const char* s = getenv("PP_RHO")) p.rho = atoi(s) != 0;
