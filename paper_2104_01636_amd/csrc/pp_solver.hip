@@ -193,9 +193,10 @@ struct Hier {
 struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 3, coarse_sweeps = 16;
     int kit2 = 0;               // K-cycle steps on levels >= 2 (0: kit)
-    int nuv = 0;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
+    int nuv = 1;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
     int nu1 = 0;                // sweeps on level 1 (0: nuc)
     bool tail = true;           // run the small coarse V-levels in one launch
+    int tail_max = 1024;        // largest level the one-launch cycle starts on (at most kTailMaxCells)
     double wc = 2.0;
     bool graphs = true;
     double omega = 1.0;         // SOR factor of the red-black smoother
@@ -487,7 +488,7 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
             // ones (iterates and operators in LDS) at most kTailSmallCells together
             int t = nl - 1;
             size_t later = 0;
-            while (t - 1 >= 1 && !Hh.L[t - 1].kcyc && Hh.L[t - 1].n <= (size_t)kTailMaxCells &&
+            while (t - 1 >= 1 && !Hh.L[t - 1].kcyc && Hh.L[t - 1].n <= (size_t)prm.tail_max &&
                    (Hh.L[t - 1].nx % 2) == 0 && later + Hh.L[t].n <= (size_t)kTailSmallCells) {
                 later += Hh.L[t].n;
                 --t;
@@ -1163,6 +1164,8 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (cfg && (cfg->flags & PP_FLAG_MG_SOLVER)) {
         p.mg_solver = true;
         p.kmax = 0;  // plain V-cycles: no Krylov steps anywhere in this form
+        p.nuv = 0;   // and post_sweeps (default 2) on every coarse level: as a stationary
+                     // iteration the cycle needs them (with one sweep it diverges)
     }
     if (const char* s = getenv("PP_KMAX")) p.kmax = atoi(s);
     if (const char* s = getenv("PP_KIT")) p.kit = std::max(1, atoi(s));
@@ -1171,6 +1174,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
     if (const char* s = getenv("PP_TAIL")) p.tail = atoi(s) != 0;
+    if (const char* s = getenv("PP_TAILMAX")) p.tail_max = std::max(2, std::min(kTailMaxCells, atoi(s)));
     if (const char* s = getenv("PP_OMEGA")) p.omega = atof(s);
     if (const char* s = getenv("PP_KIT2")) p.kit2 = std::max(0, atoi(s));
     if (const char* s = getenv("PP_NUV")) p.nuv = std::max(0, atoi(s));
