@@ -99,7 +99,7 @@ __device__ inline double wave_sum(double x)
 template <int NV>
 __device__ inline void reduce_finish(double (&v)[NV], const Reduce& R)
 {
-    __shared__ double sh[NV][kBlock / 64];
+    __shared__ double sh[NV][16];  // up to 1024 threads
     const int nthr = blockDim.x * blockDim.y * blockDim.z;
     const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
     const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);

@@ -64,6 +64,12 @@ __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_b
 // outside the grid) so that apply may use wavefront shuffles.  val at a
 // neighbour must not be changed by the pass itself (the callers write other
 // arrays, or only cells of the colour that val is not read at).
+// Threads of a march block: 256, or 512 for float64 on the finest level (tiles
+// of 64 x 8: two halo rows for eight tile rows instead of for four; measured
+// faster for the float64 kernels, slower for the float32 ones).
+template <class T, bool RHO>
+constexpr int kMarchThreads = (RHO && sizeof(T) == 8) ? 512 : kBlock;
+
 // Register sets of plane loads (loads are issued kMarchSets - 1 planes ahead
 // of the plane being computed).
 constexpr int kMarchSets = 2;
@@ -93,7 +99,7 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
     using Raw = typename Op::Raw;
     using Ex = typename Op::Ex;
     using Regs = PlaneRegs<T, Raw, Ex>;
-    constexpr int BY = kBlock / BX;
+    constexpr int BY = kMarchThreads<T, RHO> / BX;
     static_assert(BX >= 2 && BY >= 2, "a thread is on at most one x edge and one y edge of the tile");
     __shared__ T sv[2][BY][BX];
     __shared__ T swx[2][BY][BX];
@@ -375,7 +381,7 @@ struct OpRestrict {
 // ---------------------------------------------------------------- kernels
 
 template <class T, int BX, bool RHO>
-__global__ void __launch_bounds__(kBlock) m_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
+__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
                                                         int xcd, T omega)
 {
     OpFirst<T> op{f, L.invd, x, omega};
@@ -384,7 +390,7 @@ __global__ void __launch_bounds__(kBlock) m_smooth_first(LevelView<T> L, const T
 }
 
 template <class T, int BX, bool RHO, int NDOT, class TQ>
-__global__ void __launch_bounds__(kBlock) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
+__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
                                                        int xcd, const TQ* __restrict__ q, Reduce R, T omega)
 {
     OpHalf<T, NDOT, TQ> op{f, L.invd, x, q, colour, omega};
@@ -394,7 +400,7 @@ __global__ void __launch_bounds__(kBlock) m_smooth_half(LevelView<T> L, const T*
 }
 
 template <class T, int BX, bool RHO>
-__global__ void __launch_bounds__(kBlock) m_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
+__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                              T* __restrict__ rc, int kper, int xcd)
 {
     static_assert(BX <= 32, "the 2x2 sum pairs rows within one wavefront");
@@ -406,7 +412,7 @@ __global__ void __launch_bounds__(kBlock) m_residual_restrict(LevelView<T> L, co
 }
 
 template <class T, int BX, bool RHO>
-__global__ void __launch_bounds__(kBlock) m_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
+__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                          const T* __restrict__ e, T wc, T* __restrict__ y, int kper, int xcd,
                                                          T omega)
 {
@@ -416,7 +422,7 @@ __global__ void __launch_bounds__(kBlock) m_prolong_black(LevelView<T> L, const 
 }
 
 template <class T, int BX, bool RHO, class TZ, bool BETA, bool FINE>
-__global__ void __launch_bounds__(kBlock) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
+__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
                                                      T* __restrict__ x, Coefs beta, Coefs mean, int use_mean, Coefs aprev,
                                                      int kper, int xcd, Reduce R)
@@ -429,7 +435,7 @@ __global__ void __launch_bounds__(kBlock) m_dir_apply(LevelView<T> L, const TZ* 
 }
 
 template <int BX, bool RHO>
-__global__ void __launch_bounds__(kBlock) m_true_residual(LevelView<double> L, const double* __restrict__ f,
+__global__ void __launch_bounds__((kMarchThreads<double, RHO>)) m_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                          const double* __restrict__ x, double* __restrict__ r, int kper, int xcd,
                                                          Reduce R)
 {

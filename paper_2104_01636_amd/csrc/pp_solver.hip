@@ -91,11 +91,12 @@ struct MGeo {
     int kper, bx;
 };
 
-static MGeo mgeo(int nx, int ny, int nz, int bx_max, bool even_k = false, int max_blocks = kMaxRedBlocks)
+static MGeo mgeo(int nx, int ny, int nz, int bx_max, bool even_k = false, int max_blocks = kMaxRedBlocks,
+                 int threads = kBlock)
 {
     int bx = 8;
     while (bx < nx && bx < bx_max) bx <<= 1;
-    const int by = kBlock / bx;
+    const int by = threads / bx;
     const int gx = (nx + bx - 1) / bx, gy = (ny + by - 1) / by;
     const int tiles = gx * gy;
     int gz = std::max(1, std::min(nz, max_blocks / std::max(1, tiles)));
@@ -203,7 +204,8 @@ struct Params {
     bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
     bool march = true;          // plane-marching stencil kernels (else one thread per cell column)
     int mbx = 64;               // widest march tile in x
-    int mblocks = 768;          // blocks of a march launch (at most; z split to reach it)
+    int mblocks = 768;          // blocks of a 256-thread march launch (at most; z split to reach it)
+    int fblocks = 512;          // blocks of a 512-thread (finest-level float64) march launch
     int xcd = 2;                // XCD-aware tile order: 0 never, 1 always, 2 below the finest level
     bool rho = true;            // finest-level march kernels form the weights from the density
 };
@@ -613,6 +615,15 @@ static int xcd_of(const Handle* H, const LevelView<T>& v)
     return H->prm.xcd == 1 || (H->prm.xcd == 2 && n < ((size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz));
 }
 
+// Geometry of a march launch on view v (block size as in kMarchThreads).
+template <class T>
+static MGeo march_geo(const Handle* H, const LevelView<T>& v, int bx_max, bool even_k = false)
+{
+    if (v.rho && kMarchThreads<T, true> != kBlock)
+        return mgeo(v.nx, v.ny, v.nz, bx_max, even_k, H->prm.fblocks, kMarchThreads<T, true>);
+    return mgeo(v.nx, v.ny, v.nz, bx_max, even_k, H->prm.mblocks, kBlock);
+}
+
 // Launchers: the plane-march kernels, or the per-column kernels when the march is off.
 
 template <class T>
@@ -620,7 +631,7 @@ static void launch_first(Handle* H, const LevelView<T>& v, const T* f, T* x)
 {
     const T om = (T)H->prm.omega;
     if (H->prm.march) {
-        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
             with_rho(v, [&](auto R) {
                 m_smooth_first<T, decltype(B)::value, decltype(R)::value><<<g.grid, g.block, 0, H->stream>>>(v, f, x, g.kper,
@@ -641,7 +652,7 @@ static dim3 launch_half(Handle* H, const LevelView<T>& v, const T* f, T* x, int 
 {
     const T om = (T)H->prm.omega;
     if (H->prm.march) {
-        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
             with_rho(v, [&](auto W) {
                 m_smooth_half<T, decltype(B)::value, decltype(W)::value, NDOT, TQ>
@@ -661,7 +672,7 @@ template <class T>
 static void launch_restrict(Handle* H, const LevelView<T>& v, const T* f, const T* x, T* rc)
 {
     if (H->prm.march) {
-        const MGeo g = mgeo(v.nx, v.ny, v.nz, std::min(H->prm.mbx, 32), true, H->prm.mblocks);
+        const MGeo g = march_geo(H, v, std::min(H->prm.mbx, 32), true);
         with_bx_le32(g.bx, [&](auto B) {
             with_rho(v, [&](auto R) {
                 m_residual_restrict<T, decltype(B)::value, decltype(R)::value>
@@ -680,7 +691,7 @@ static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, c
 {
     const T om = (T)H->prm.omega;
     if (H->prm.march) {
-        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
             with_rho(v, [&](auto R) {
                 m_prolong_black<T, decltype(B)::value, decltype(R)::value>
@@ -700,7 +711,7 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
                        Coefs beta, int use_beta, Coefs mean, int use_mean, Coefs aprev, const Reduce& R)
 {
     if (H->prm.march) {
-        const MGeo g = mgeo(v.nx, v.ny, v.nz, H->prm.mbx, false, H->prm.mblocks);
+        const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
             with_rho(v, [&](auto W) {
                 constexpr int BX = decltype(B)::value;
@@ -1062,7 +1073,7 @@ static double true_residual(Handle* H, const double* x)
         TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * (24.0 + 8.0 * weight_arrays(H, v)));
         const Reduce R = red(H, G_TRR, G_TRSUM);
         if (H->prm.march) {
-            const MGeo g = mgeo(cfg.nx, cfg.ny, cfg.nz, H->prm.mbx, false, H->prm.mblocks);
+            const MGeo g = march_geo(H, v, H->prm.mbx);
             with_bx(g.bx, [&](auto B) {
                 with_rho(v, [&](auto W) {
                     m_true_residual<decltype(B)::value, decltype(W)::value>
@@ -1076,7 +1087,7 @@ static double true_residual(Handle* H, const double* x)
         check_launch();
     }
     {
-        const dim3 grid = H->prm.march ? mgeo(cfg.nx, cfg.ny, cfg.nz, H->prm.mbx, false, H->prm.mblocks).grid
+        const dim3 grid = H->prm.march ? march_geo(H, v, H->prm.mbx).grid
                                        : geo(cfg.nx, cfg.ny, cfg.nz).grid;
         finish(H, red(H, G_TRR, G_TRSUM), grid, 2);
     }
@@ -1182,6 +1193,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_MARCH")) p.march = atoi(s) != 0;
     if (const char* s = getenv("PP_XCD")) p.xcd = atoi(s);
     if (const char* s = getenv("PP_RHO")) p.rho = atoi(s) != 0;
+    if (const char* s = getenv("PP_FBLOCKS")) p.fblocks = std::max(32, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBLOCKS")) p.mblocks = std::max(64, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBX")) {
         const int b = atoi(s);
