@@ -197,6 +197,8 @@ struct Params {
     int nuv = 1;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
     int nu1 = 0;                // sweeps on level 1 (0: nuc)
     bool tail = true;           // run the small coarse V-levels in one launch
+    int kmin = 65536;           // K-cycles only on levels with more cells than this (smaller ones: V-cycles,
+                                // whose launches cost less than the iterations they save)
     int tail_max = 1024;        // largest level the one-launch cycle starts on (at most kTailMaxCells)
     double wc = 2.0;
     bool graphs = true;
@@ -440,7 +442,7 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         for (int l = 0; l < nl; ++l) {
             Lev<T>& V = Hh.L[l];
             V.nx = nx[l]; V.ny = ny[l]; V.nz = nz[l]; V.n = nn(l);
-            V.kcyc = (l >= 1 && l <= prm.kmax && l < nl - 1);
+            V.kcyc = (l >= 1 && l <= prm.kmax && l < nl - 1 && V.n > (size_t)prm.kmin);
             if (!alloc) continue;
             if (l > 0) V.rhs = P.template take<T>(V.n);
             V.c = P.template take<T>(V.n);
@@ -1179,6 +1181,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
                      // iteration the cycle needs them (with one sweep it diverges)
     }
     if (const char* s = getenv("PP_KMAX")) p.kmax = atoi(s);
+    if (const char* s = getenv("PP_KMIN")) p.kmin = std::max(0, atoi(s));
     if (const char* s = getenv("PP_KIT")) p.kit = std::max(1, atoi(s));
     if (const char* s = getenv("PP_WC")) p.wc = atof(s);
     if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
