@@ -193,7 +193,9 @@ struct Hier {
 
 struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 3, coarse_sweeps = 16;
-    int kit2 = 0;               // K-cycle steps on levels >= 2 (0: kit)
+    int kit2 = 4;               // K-cycle steps on levels >= 2 (0: kit)
+    int nuk2 = 1;               // sweeps on the K-cycle levels >= 2 (0: nuc); the extra
+                                // K-cycle step there buys more than the second sweep
     int nuv = 1;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
     int nu1 = 0;                // sweeps on level 1 (0: nuc)
     bool tail = true;           // run the small coarse V-levels in one launch
@@ -794,6 +796,7 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     }
     const int nu = fine ? H->prm.nu0
                : (l == 1 && H->prm.nu1 > 0)                            ? H->prm.nu1
+               : (V.kcyc && l >= 2 && H->prm.nuk2 > 0)                 ? H->prm.nuk2
                : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0)        ? H->prm.nuv
                                                                        : H->prm.nuc;
     {
@@ -1193,6 +1196,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_KIT2")) p.kit2 = std::max(0, atoi(s));
     if (const char* s = getenv("PP_NUV")) p.nuv = std::max(0, atoi(s));
     if (const char* s = getenv("PP_NU1")) p.nu1 = std::max(0, atoi(s));
+    if (const char* s = getenv("PP_NUK2")) p.nuk2 = std::max(0, atoi(s));
     if (const char* s = getenv("PP_MARCH")) p.march = atoi(s) != 0;
     if (const char* s = getenv("PP_XCD")) p.xcd = atoi(s);
     if (const char* s = getenv("PP_RHO")) p.rho = atoi(s) != 0;
