@@ -89,6 +89,12 @@ struct PlaneRegs {
 __device__ inline double face_beta(double a, double b) { return 2.0 / (a + b); }
 __device__ inline float face_beta(float a, float b) { return 2.0f * __builtin_amdgcn_rcpf(a + b); }
 
+// Gauss-Seidel value (s + f) / D at a cell whose diagonal D is the sum of its
+// face weights (the stencil's own d): no 1/D array is read.  Float64 divides;
+// float32 (preconditioner only) multiplies by the hardware reciprocal.
+__device__ inline double gs_value(double s, double f, double d) { return (s + f) / d; }
+__device__ inline float gs_value(float s, float f, float d) { return (s + f) * __builtin_amdgcn_rcpf(d); }
+
 // RHO: the level is the finest and its face weights are formed from L.rho
 // (the x and y weights of a cell from the LDS copy of the plane's density,
 // the z weight from the density of the next plane) instead of read from
@@ -249,23 +255,23 @@ struct OpFirst {  // red-black SOR from a zero guess (red omega f/D, black one u
 
 template <class T, int NDOT, class TQ>
 struct OpHalf {  // one colour of a red-black SOR sweep in place; optional dots
-    const T *f, *invd;
+    const T* f;
     T* x;
     const TQ* q;
     int colour;
     T omega;
     using Raw = T;
-    struct Ex { T f, invd; TQ q; };
+    struct Ex { T f; TQ q; };
     __device__ Raw load(int c, int, int, int) const { return x[c]; }
     __device__ T val(Raw a) const { return a; }
-    __device__ Ex extra(int c) const { return {f[c], invd[c], NDOT >= 2 ? q[c] : TQ(0)}; }
+    __device__ Ex extra(int c) const { return {f[c], NDOT >= 2 ? q[c] : TQ(0)}; }
     template <class A>
     __device__ void apply(int c, int i, int j, int k, T vc, Raw, const Ex& e, const Stencil<T>& st, A& acc, bool act) const
     {
         if (!act) return;
         T xv = vc;
         if (((i + j + k) & 1) == colour) {
-            xv = (st.s + e.f) * e.invd;
+            xv = gs_value(st.s, e.f, st.d);
             if (omega != T(1)) xv = vc + omega * (xv - vc);
             x[c] = xv;
         }
@@ -276,23 +282,23 @@ struct OpHalf {  // one colour of a red-black SOR sweep in place; optional dots
 
 template <class T>
 struct OpProlongBlack {  // y = x + wc P e on red cells; black SOR update from them
-    const T *f, *invd, *x, *e;
+    const T *f, *x, *e;
     T* y;
     T wc, omega;
     int cnx, cny;
     struct Raw { T x, e; };
-    struct Ex { T f, invd; };
+    using Ex = T;  // f
     __device__ Raw load(int c, int i, int j, int k) const { return {x[c], e[cell(cnx, cny, i >> 1, j >> 1, k >> 1)]}; }
     __device__ T val(const Raw& a) const { return a.x + wc * a.e; }
-    __device__ Ex extra(int c) const { return {f[c], invd[c]}; }
+    __device__ Ex extra(int c) const { return f[c]; }
     template <class A>
-    __device__ void apply(int c, int i, int j, int k, T vc, const Raw&, const Ex& ex, const Stencil<T>& st, A&, bool act) const
+    __device__ void apply(int c, int i, int j, int k, T vc, const Raw&, const Ex& fc, const Stencil<T>& st, A&, bool act) const
     {
         if (!act) return;
         if (((i + j + k) & 1) == 0) {
             y[c] = vc;
         } else {
-            T gs = (st.s + ex.f) * ex.invd;
+            T gs = gs_value(st.s, fc, st.d);
             if (omega != T(1)) gs = vc + omega * (gs - vc);
             y[c] = gs;
         }
@@ -393,7 +399,7 @@ template <class T, int BX, bool RHO, int NDOT, class TQ>
 __global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
                                                        int xcd, const TQ* __restrict__ q, Reduce R, T omega)
 {
-    OpHalf<T, NDOT, TQ> op{f, L.invd, x, q, colour, omega};
+    OpHalf<T, NDOT, TQ> op{f, x, q, colour, omega};
     double acc[NDOT > 0 ? NDOT : 1] = {};
     march<T, BX, RHO>(L, kper, xcd, op, acc);
     if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
@@ -416,7 +422,7 @@ __global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_prolong_black(Level
                                                          const T* __restrict__ e, T wc, T* __restrict__ y, int kper, int xcd,
                                                          T omega)
 {
-    OpProlongBlack<T> op{f, L.invd, x, e, y, wc, omega, L.nx >> 1, L.ny >> 1};
+    OpProlongBlack<T> op{f, x, e, y, wc, omega, L.nx >> 1, L.ny >> 1};
     double acc[1] = {0.0};
     march<T, BX, RHO>(L, kper, xcd, op, acc);
 }

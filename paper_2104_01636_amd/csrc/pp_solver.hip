@@ -151,6 +151,7 @@ static inline int lslot(int l, int s) { return l * kLevSlots + s; }
 
 constexpr int kMaxLev = 24;
 constexpr int kDenseMax = 128;
+static_assert(kDenseMax <= kTailDenseMax, "the tail's dense product covers the coarsest level");
 
 // ---------------------------------------------------------------- arena plan
 
@@ -513,6 +514,9 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
                 D.L[l - t].off = off;
                 if (l > t) off += (int)V.n;
             }
+            // the first level joins the later ones in LDS when it fits beside them
+            D.lds0 = (size_t)off + Hh.L[t].n <= (size_t)kTailSmallCells;
+            D.off0 = off;
             D.Minv = Hh.Minv;
             D.nd = Hh.nd;
             D.wc = prm.wc;
@@ -600,6 +604,10 @@ static double weight_arrays(const Handle* H, const LevelView<T>& v)
 {
     return (v.rho && H->prm.march) ? 1.0 : 3.0;
 }
+
+// 1/D arrays read by a half-sweep or prolongation: the march kernels divide by
+// the stencil's own diagonal, the per-cell kernels read 1/D.
+static double invd_arrays(const Handle* H) { return H->prm.march ? 0.0 : 1.0; }
 
 template <bool B>
 using RhoC = std::integral_constant<bool, B>;
@@ -744,9 +752,11 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
     Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
     dim3 grid;
     {
-        // reads x, f, 1/D and the weights (or the density); writes one colour (and reads q for the dot)
+        // reads x, f and the weights (or the density; the per-cell kernels also 1/D); writes one
+        // colour (and reads q for the dot)
         TimeScope ts(H, fine ? kid<T>(ndot ? KT_SMOOTH_HALF_DOT : KT_SMOOTH_HALF) : -1,
-                     (double)V.n * ((3.5 + weight_arrays(H, V.v)) * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
+                     (double)V.n * ((2.5 + invd_arrays(H) + weight_arrays(H, V.v)) * sizeof(T) +
+                                    (ndot >= 2 ? sizeof(TQ) : 0)));
         if (ndot == 0) grid = launch_half<T, 0, TQ>(H, V.v, f, x, colour, q, R);
         else if (ndot == 1) grid = launch_half<T, 1, TQ>(H, V.v, f, x, colour, q, R);
         else grid = launch_half<T, 2, TQ>(H, V.v, f, x, colour, q, R);
@@ -767,7 +777,8 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     const bool fine = (l == 0);
     const int last = (int)Hh.L.size() - 1;
     if (l == Hh.tail && l > 0) {
-        k_tail_vcycle<T><<<1, kTailThreads, 0, H->stream>>>(Hh.td);
+        if (Hh.td.lds0) k_tail_vcycle<T, true><<<1, kTailThreads, 0, H->stream>>>(Hh.td);
+        else k_tail_vcycle<T, false><<<1, kTailThreads, 0, H->stream>>>(Hh.td);
         check_launch();
         return V.c;
     }
@@ -824,8 +835,10 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         wc = (T)H->prm.wc;
     }
     {
-        // reads x, f, 1/D, the weights (or the density) and the coarse correction; writes y
-        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1, (double)V.n * sizeof(T) * (4.125 + weight_arrays(H, V.v)));
+        // reads x, f, the weights (or the density) and the coarse correction (the per-cell
+        // kernels also 1/D); writes y
+        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1,
+                     (double)V.n * sizeof(T) * (3.125 + invd_arrays(H) + weight_arrays(H, V.v)));
         launch_prolong_black<T>(H, V.v, f, V.c, e, wc, V.c2);
     }
     T* cur = V.c2;

@@ -3,8 +3,10 @@
 // Below a few thousand cells a grid launch per smoothing pass costs more than
 // the pass itself, so the V-cycle over the last levels runs in one work-group
 // of 1024 threads.  The iterates of every level and the whole operator of the
-// levels after the first stay in LDS (the first level's face weights, 1/D and
-// right-hand side are read from global memory, where they are L2-resident).
+// levels after the first stay in LDS.  When the first level fits beside them
+// its operator and right-hand side are staged in LDS as well, so the cycle
+// waits for global memory once; otherwise (a first level of up to 8192 cells)
+// they are read from global memory, where they are L2-resident.
 // Each thread owns fixed x-pairs (2m, 2m+1) of the first level, with their
 // indices and boundary flags computed once; a half-sweep touches only the cell
 // of the pair that has the colour being relaxed.  Boundaries are handled
@@ -16,6 +18,8 @@
 // 8 children, injection prolongation of the correction scaled by wc, and the
 // dense inverse (or symmetric sweeps) on the last level.
 #pragma once
+#include <type_traits>
+
 #include "pp_kernels.hpp"
 
 namespace pp {
@@ -24,6 +28,8 @@ constexpr int kTailMaxLev = 12;
 constexpr int kTailThreads = 1024;
 constexpr int kTailMaxCells = 8192;                               // first tail level at most this large
 constexpr int kTailSmallCells = 1200;                             // cells of the later levels (8192/7 < 1200)
+constexpr int kTailDenseMax = 128;                                // rows of the dense inverse on the last level
+constexpr int kTailDenseSplit = kTailThreads / kTailDenseMax;     // column chunks of its product
 
 template <class T>
 struct TailLevel {
@@ -42,6 +48,8 @@ struct TailDesc {
     int nd;
     T wc, omega;
     int nu, coarse_sweeps;
+    int lds0;       // the first level's operator and right-hand side are staged in LDS
+    int off0;       // their offset in the LDS arrays (after the later levels)
 };
 
 // x / d for 0 <= x < 2^22 and d > 0 from a float reciprocal, corrected to the
@@ -205,8 +213,8 @@ __device__ inline void pair_cell(int pk, int colour, int& c, int& fl)
 // Half-sweep of the first level: kTailBatch pairs per thread and round (4 in
 // float32, 2 in float64, as registers allow), all loads of their cells issued
 // before any is computed (the cells of one colour are independent).
-template <class T>
-__device__ inline void tail_half_first(const TailG<T>& a, const int* pinfo, int np, int colour, T omega)
+template <class T, class A>
+__device__ inline void tail_half_first(const A& a, const int* pinfo, int np, int colour, T omega)
 {
     constexpr int kTailBatch = sizeof(T) == 4 ? 4 : 2;
     for (int t = threadIdx.x; t < np; t += kTailBatch * kTailThreads) {
@@ -316,20 +324,25 @@ __device__ inline void tail_prolong_small(const TailS<T>& a, const T* e, T wc)
 }
 
 // One V-cycle over the levels of D from a zero guess at the top; the result is
-// left in D.L[0].c.
+// left in D.L[0].c.  LDS0: the first level's operator and right-hand side are
+// staged in LDS (D.lds0) instead of read from global memory.
 // (one block of 16 wavefronts: 4 per SIMD is all the occupancy there is, so the
 // compiler may spend registers on keeping loads in flight)
-template <class T>
+template <class T, bool LDS0>
 __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) k_tail_vcycle(TailDesc<T> D)
 {
     __shared__ T x0[kTailMaxCells];
     __shared__ T sxs[kTailSmallCells], swx[kTailSmallCells], swy[kTailSmallCells], swz[kTailSmallCells],
         sid[kTailSmallCells], sf[kTailSmallCells];
     __shared__ int pinfo[kTailMaxCells / 2];
+    __shared__ T dpart[kTailThreads];
     const int last = D.nlev - 1;
     const T om = D.omega;
+    const TailLevel<T>& V0 = D.L[0];
 
-    // stage the operators of the later levels
+    // stage the operators of the later levels (and, with LDS0, the first level's
+    // operator and right-hand side after them): every load of the cycle but the
+    // dense inverse is issued here
     for (int l = 1; l <= last; ++l) {
         const TailLevel<T>& V = D.L[l];
         for (int c = threadIdx.x; c < V.n; c += kTailThreads) {
@@ -339,13 +352,27 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
             sid[V.off + c] = ldg(V.v.invd, c);
         }
     }
+    if constexpr (LDS0) {
+        for (int c = threadIdx.x; c < V0.n; c += kTailThreads) {
+            swx[D.off0 + c] = ldg(V0.v.wx, c);
+            swy[D.off0 + c] = ldg(V0.v.wy, c);
+            swz[D.off0 + c] = ldg(V0.v.wz, c);
+            sid[D.off0 + c] = ldg(V0.v.invd, c);
+            sf[D.off0 + c] = ldg(V0.rhs, c);
+        }
+    }
 #define PP_TAIL_SMALL(l)                                                                                          \
     TailS<T>{swx + D.L[l].off, swy + D.L[l].off, swz + D.L[l].off, sid + D.L[l].off, sf + D.L[l].off, sxs + D.L[l].off, \
              D.L[l].v.nx, D.L[l].v.ny, D.L[l].v.nz}
 
     // first level: pairs, sweeps from zero, restriction into level 1
-    const TailLevel<T>& V0 = D.L[0];
-    const TailG<T> g{V0.v.wx, V0.v.wy, V0.v.wz, V0.v.invd, V0.rhs, x0, V0.v.nx, V0.v.ny, V0.v.nz};
+    using First = std::conditional_t<LDS0, TailS<T>, TailG<T>>;
+    First g;
+    if constexpr (LDS0) {
+        g = TailS<T>{swx + D.off0, swy + D.off0, swz + D.off0, sid + D.off0, sf + D.off0, x0, V0.v.nx, V0.v.ny, V0.v.nz};
+    } else {
+        g = TailG<T>{V0.v.wx, V0.v.wy, V0.v.wz, V0.v.invd, V0.rhs, x0, V0.v.nx, V0.v.ny, V0.v.nz};
+    }
     const int np0 = V0.n >> 1;
     tail_pairs(V0.v, pinfo);
     __syncthreads();  // also completes the staging above
@@ -392,10 +419,31 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
         const TailS<T> b = PP_TAIL_SMALL(last);
         const int n = D.L[last].n;
         if (D.nd > 0) {
-            for (int r = threadIdx.x; r < D.nd; r += kTailThreads) {
-                T acc = T(0);
-                for (int c = 0; c < D.nd; ++c) acc += ldg(D.Minv, c * D.nd + r) * b.sf[c];
-                b.xs[r] = acc;
+            // x = Minv f (nd <= kTailDenseMax): thread t forms row t mod kTailDenseMax
+            // over one chunk of the columns, with all of its loads issued together;
+            // the chunks are then added in a fixed order
+            constexpr int kPer = kTailDenseMax / kTailDenseSplit;
+            const int nd = D.nd;
+            const int r = threadIdx.x % kTailDenseMax, c0 = (threadIdx.x / kTailDenseMax) * kPer;
+            T m[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int c = c0 + u;
+                m[u] = (r < nd && c < nd) ? ldg(D.Minv, c * nd + r) : T(0);
+            }
+            T acc = T(0);
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int c = c0 + u;
+                acc += m[u] * (c < nd ? b.sf[c] : T(0));
+            }
+            dpart[threadIdx.x] = acc;
+            __syncthreads();
+            if (threadIdx.x < nd) {
+                T x = T(0);
+#pragma unroll
+                for (int h = 0; h < kTailDenseSplit; ++h) x += dpart[h * kTailDenseMax + threadIdx.x];
+                b.xs[threadIdx.x] = x;
             }
             __syncthreads();
         } else {

@@ -144,6 +144,26 @@ def test_duct32_against_reference(mode):
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("env", [{"PP_TAILMAX": "8192"}, {"PP_TAIL": "0"}], ids=["tail_from_8192", "no_tail"])
+def test_duct32_cycle_variants(mode, env, monkeypatch):
+    """The other coarse-level paths, read from the environment when the handle is
+    made: a one-launch tail from the 8192-cell level (its first level read from
+    global memory) and no tail (a launch per pass, dense product on its own)."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    case = W.preset("duct32")
+    say("duct32", mode, env)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    p_ref, it, rr_ref, _ = cref.solve(rho_ref, b_ref, case.h, tol=1e-13)
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=1e-10) as S:
+        S.set_density(rho_t)
+        p, st = S.solve(b_t)
+        p = cpu(p)
+    rr, err = check_solution(rho_ref, b_ref, case.h, p, 1e-10, p_ref)
+    say("   iters", st["iters"], st["inner_iters_total"], "res", rr, "err", err, "ms", st["solve_ms"])
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
 def test_duct128_against_reference(mode):
     case = W.preset("duct128")
     say("duct128", mode)
