@@ -78,7 +78,7 @@ constexpr int kMarchSets = 2;
 // the halo neighbour values (raw) and halo weights, and the raw inputs at k+1.
 template <class T, class Raw, class Ex>
 struct PlaneRegs {
-    T wx, wy, wz, wxh, wyh;  // weights from memory; with the density: rho, -, rho at k+1, halo rho x, halo rho y
+    T wx, wy, wz, wxh, wyh;  // weights from memory; with the density: -, -, rho at k+1, halo rho x, halo rho y
     Raw rx, ry, rn;
     Ex ex;
 };
@@ -133,7 +133,8 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
     auto fetch = [&](Regs& S, int k, int c) {
         const int kt = k < L.nz - 1 ? k + 1 : 0;
         if constexpr (RHO) {
-            S.wx = L.rho[c];
+            // the cell's own density is the previous plane's z load (carried in rho_c)
+            S.wx = T(0);
             S.wy = T(0);
             S.wz = L.rho[c + (kt - k) * sz];
             S.wxh = L.rho[c + oi];
@@ -156,8 +157,13 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
     int c = cell(L.nx, L.ny, ic, jc, k0);
     const T vm0 = op.val(op.load(c + (kb0 - k0) * sz, ic, jc, kb0));
     T wzb;
-    if constexpr (RHO) wzb = face_beta(L.rho[c + (kb0 - k0) * sz], L.rho[c]);
-    else wzb = L.wz[c + (kb0 - k0) * sz];
+    T rho_c = T(0);  // RHO: density of the current plane's cell
+    if constexpr (RHO) {
+        rho_c = L.rho[c];
+        wzb = face_beta(L.rho[c + (kb0 - k0) * sz], rho_c);
+    } else {
+        wzb = L.wz[c + (kb0 - k0) * sz];
+    }
     Raw rc = op.load(c, ic, jc, k0);
     // kMarchSets register sets: plane k is in set (k - k0) mod kMarchSets and the
     // loads of plane k + kMarchSets - 1 are issued while plane k is computed
@@ -181,7 +187,7 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
         const T vyh = hy ? op.val(S.ry) : T(0);
         sv[buf][ty][tx] = vc;
         if constexpr (RHO) {
-            swx[buf][ty][tx] = act ? S.wx : T(1);
+            swx[buf][ty][tx] = act ? rho_c : T(1);
         } else {
             swx[buf][ty][tx] = act ? S.wx : T(0);
             swy[buf][ty][tx] = act ? S.wy : T(0);
@@ -194,7 +200,7 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
         T ww, we, ws, wn, wt;
         if constexpr (RHO) {
             // neighbour densities: LDS inside the tile, the halo value on its edge
-            const T rc = S.wx;
+            const T rc = rho_c;
             const T rw = tx > 0 ? swx[buf][ty][tx - 1] : S.wxh;
             const T re = tx < BX - 1 ? swx[buf][ty][tx + 1] : S.wxh;
             const T rs = ty > 0 ? swx[buf][ty - 1][tx] : S.wyh;
@@ -219,6 +225,7 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
         vc = vp;
         rc = S.rn;
         wzb = wt;
+        if constexpr (RHO) rho_c = S.wz;
     };
 
     // kMarchSets planes per trip so that the register sets rotate without copies
