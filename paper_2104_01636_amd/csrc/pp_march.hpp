@@ -28,6 +28,7 @@ template <class T>
 struct Stencil {
     T s;  // sum_f W_f v_nb(f)
     T d;  // sum_f W_f = D_c
+    T ww, we, ws, wn, wb, wt;  // the face weights themselves (zero on walls)
 };
 
 struct None {};
@@ -99,13 +100,21 @@ __device__ inline float gs_value(float s, float f, float d) { return (s + f) * _
 // (the x and y weights of a cell from the LDS copy of the plane's density,
 // the z weight from the density of the next plane) instead of read from
 // L.wx, L.wy, L.wz: 8 bytes per cell in float64 instead of 24.
-template <class T, int BX, bool RHO, class Op, class Acc>
+//
+// OVL (overlapped tiles, for operations that need values two cells away): the
+// block's NT threads cover BX x BY cells of which the inner (BX-2) x (BY-2) are
+// its own, tiles step by the inner size, the outer ring is computed again by
+// the neighbouring blocks, and the march runs one plane below and one above
+// the block's z range (periodic in z).  apply then sees ring cells and the two
+// extra planes as well; cells outside the grid have act false.
+template <class T, int BX, bool RHO, bool OVL = false, int NT = kMarchThreads<T, RHO>, class Op, class Acc>
 __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, Acc& acc)
 {
     using Raw = typename Op::Raw;
     using Ex = typename Op::Ex;
     using Regs = PlaneRegs<T, Raw, Ex>;
-    constexpr int BY = kMarchThreads<T, RHO> / BX;
+    constexpr int BY = NT / BX;
+    constexpr int SX = OVL ? BX - 2 : BX, SY = OVL ? BY - 2 : BY, OFS = OVL ? 1 : 0;
     static_assert(BX >= 2 && BY >= 2, "a thread is on at most one x edge and one y edge of the tile");
     __shared__ T sv[2][BY][BX];
     __shared__ T swx[2][BY][BX];
@@ -113,15 +122,19 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
     const int tx = threadIdx.x, ty = threadIdx.y;
     int bx, by, bz;
     tile_of_block(bx, by, bz, xcd);
-    const int i = bx * BX + tx, j = by * BY + ty;
+    const int i = bx * SX + tx - OFS, j = by * SY + ty - OFS;
     const int k0 = bz * kper, k1 = min(L.nz, k0 + kper);
-    const bool act = i < L.nx && j < L.ny;
+    // planes marched, as virtual indices v (the plane is v mod nz with OVL)
+    const int vlo = OVL ? k0 - 1 : k0, vhi = OVL ? k1 + 1 : k1;
+    const bool act = i >= 0 && j >= 0 && i < L.nx && j < L.ny;
     const int sy = L.nx, sz = L.nx * L.ny;
     // Every load is issued by every lane at an address inside the grid (threads
     // outside it read the nearest cell, edge threads without a halo neighbour
     // read their own cell) and unused values are discarded: each plane issues
     // the same loads, so the compiler waits for exactly the ones it needs.
-    const int ic = min(i, L.nx - 1), jc = min(j, L.ny - 1);
+    const int ic = max(0, min(i, L.nx - 1)), jc = max(0, min(j, L.ny - 1));
+    const int cbase = cell(L.nx, L.ny, ic, jc, 0);
+    auto plane = [&](int v) { return OVL ? (v < 0 ? v + L.nz : (v >= L.nz ? v - L.nz : v)) : v; };
     const bool hx = act && ((tx == 0 && i > 0) || (tx == BX - 1 && i < L.nx - 1));
     const bool hy = act && ((ty == 0 && j > 0) || (ty == BY - 1 && j < L.ny - 1));
     const int oi = hx ? (tx == 0 ? -1 : 1) : 0;  // x offset of this thread's halo neighbour
@@ -152,36 +165,40 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
         S.ry = op.load(c + oj * sy, ic, jc + oj, k);
     };
 
-    // prologue: value at k0-1, value and raw inputs at k0, registers of plane k0
-    const int kb0 = k0 > 0 ? k0 - 1 : L.nz - 1;
-    int c = cell(L.nx, L.ny, ic, jc, k0);
-    const T vm0 = op.val(op.load(c + (kb0 - k0) * sz, ic, jc, kb0));
+    // prologue: value at the plane below the first, value and raw inputs at the
+    // first, registers of the first plane
+    const int ks = plane(vlo), kb0 = ks > 0 ? ks - 1 : L.nz - 1;
+    const int c = cbase + ks * sz;
+    const T vm0 = op.val(op.load(c + (kb0 - ks) * sz, ic, jc, kb0));
     T wzb;
     T rho_c = T(0);  // RHO: density of the current plane's cell
     if constexpr (RHO) {
         rho_c = L.rho[c];
-        wzb = face_beta(L.rho[c + (kb0 - k0) * sz], rho_c);
+        wzb = face_beta(L.rho[c + (kb0 - ks) * sz], rho_c);
     } else {
-        wzb = L.wz[c + (kb0 - k0) * sz];
+        wzb = L.wz[c + (kb0 - ks) * sz];
     }
-    Raw rc = op.load(c, ic, jc, k0);
-    // kMarchSets register sets: plane k is in set (k - k0) mod kMarchSets and the
-    // loads of plane k + kMarchSets - 1 are issued while plane k is computed
+    Raw rc = op.load(c, ic, jc, ks);
+    // kMarchSets register sets: plane v is in set (v - vlo) mod kMarchSets and the
+    // loads of plane v + kMarchSets - 1 are issued while plane v is computed
     Regs R[kMarchSets];
 #pragma unroll
     for (int s = 0; s < kMarchSets - 1; ++s) {
-        const bool in = k0 + s < k1;
-        fetch(R[s], in ? k0 + s : k0, in ? c + s * sz : c);
+        const bool in = vlo + s < vhi;
+        const int kf = in ? plane(vlo + s) : ks;
+        fetch(R[s], kf, cbase + kf * sz);
     }
     T vm = act ? vm0 : T(0);
     T vc = act ? op.val(rc) : T(0);
 
-    // One plane: S holds plane k, N receives plane k + kMarchSets - 1 (plane k
+    // One plane: S holds plane v, N receives plane v + kMarchSets - 1 (plane v
     // again near the block's last plane, unused).
-    auto step = [&](Regs& S, Regs& N, int k, int c, int buf) {
+    auto step = [&](Regs& S, Regs& N, int v, int buf) {
         constexpr int ahead = kMarchSets - 1;
-        const bool more = k + ahead < k1;
-        fetch(N, more ? k + ahead : k, more ? c + ahead * sz : c);
+        const int k = plane(v), c = cbase + k * sz;
+        const bool more = v + ahead < vhi;
+        const int kn = more ? plane(v + ahead) : k;
+        fetch(N, kn, cbase + kn * sz);
         const T vp = act ? op.val(S.rn) : T(0);
         const T vxh = hx ? op.val(S.rx) : T(0);
         const T vyh = hy ? op.val(S.ry) : T(0);
@@ -220,6 +237,12 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
         Stencil<T> st;
         st.s = ww * vw + we * ve + ws * vs + wn * vn + wzb * vm + wt * vp;
         st.d = ww + we + ws + wn + wzb + wt;
+        st.ww = ww;
+        st.we = we;
+        st.ws = ws;
+        st.wn = wn;
+        st.wb = wzb;
+        st.wt = wt;
         op.apply(c, i, j, k, vc, rc, S.ex, st, acc, act);
         vm = vc;
         vc = vp;
@@ -229,15 +252,15 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
     };
 
     // kMarchSets planes per trip so that the register sets rotate without copies
-    int k = k0;
-    for (; k + kMarchSets - 1 < k1; k += kMarchSets, c += kMarchSets * sz) {
+    int v = vlo;
+    for (; v + kMarchSets - 1 < vhi; v += kMarchSets) {
 #pragma unroll
         for (int s = 0; s < kMarchSets; ++s)
-            step(R[s], R[(s + kMarchSets - 1) % kMarchSets], k + s, c + s * sz, (k + s - k0) & 1);
+            step(R[s], R[(s + kMarchSets - 1) % kMarchSets], v + s, (v + s - vlo) & 1);
     }
 #pragma unroll
     for (int s = 0; s < kMarchSets - 1; ++s)
-        if (k + s < k1) step(R[s], R[(s + kMarchSets - 1) % kMarchSets], k + s, c + s * sz, (k + s - k0) & 1);
+        if (v + s < vhi) step(R[s], R[(s + kMarchSets - 1) % kMarchSets], v + s, (v + s - vlo) & 1);
 }
 
 // ---------------------------------------------------------------- operations
@@ -391,6 +414,78 @@ struct OpRestrict {
     }
 };
 
+// Overlapped tile of m_first_restrict: 32 x 16 threads, 30 x 14 cells of its own.
+constexpr int kOvlX = 32, kOvlY = 16;
+
+// The first sweep from a zero guess (as OpFirst) and the restriction of its
+// residual (as OpRestrict) in one pass.  A red cell's residual needs its black
+// neighbours' new values, and those need their red neighbours, so the block
+// computes x on its ring and on the planes below and above its range as well
+// (march with OVL), writes x for its own cells and real planes only, and forms
+// the residual one plane behind the sweep from the x values of three planes:
+// the in-plane neighbours from an LDS copy of the previous plane, the z
+// neighbours from registers.  The 2 x 2 children of a plane are lanes
+// (l, l+1) of one row (one wavefront) and rows (t, t+1) summed through LDS;
+// the two planes of a pair are consecutive steps (k0 and kper even).
+template <class T>
+struct OpFirstRestrict {
+    const T *f, *invd;
+    T* x;
+    T* rc;
+    T omega;
+    int cnx, cny, k0, nreal;  // coarse sizes, first plane and real planes of the block
+    int s = 0;                // step: plane k0 - 1 + s
+    T xm2 = T(0), xm1 = T(0), fm1 = T(0), part = T(0);  // x two and one planes back, f one back
+    T pw = T(0), pe = T(0), ps = T(0), pn = T(0), pb = T(0), pt = T(0);  // face weights one back
+    struct Raw { T f, invd; };
+    using Ex = None;
+    __device__ Raw load(int c, int, int, int) const { return {f[c], invd[c]}; }
+    __device__ T val(const Raw& a) const { return omega * (a.f * a.invd); }
+    __device__ Ex extra(int) const { return {}; }
+    template <class A>
+    __device__ void apply(int c, int i, int j, int k, T vc, const Raw& a, const Ex&, const Stencil<T>& st, A&, bool act)
+    {
+        __shared__ T sx[2][kOvlY][kOvlX];  // x of the last two planes
+        __shared__ T sr[kOvlY][kOvlX];     // restriction sums of the rows
+        const int tx = threadIdx.x, ty = threadIdx.y;
+        const T xv = act ? ((((i + j + k) & 1) == 0) ? vc : omega * ((st.s + a.f) * a.invd)) : T(0);
+        const bool own = act && tx >= 1 && tx <= kOvlX - 2 && ty >= 1 && ty <= kOvlY - 2;
+        if (own && s >= 1 && s <= nreal) x[c] = xv;
+        sx[s & 1][ty][tx] = xv;  // read at the next step, after its barrier
+        if (s >= 2) {
+            // residual of plane k0 - 2 + s (a real plane), from x of three planes
+            T r = T(0);
+            if (own) {
+                const int b = (s - 1) & 1;
+                const T nb = pw * sx[b][ty][tx - 1] + pe * sx[b][ty][tx + 1] + ps * sx[b][ty - 1][tx] +
+                             pn * sx[b][ty + 1][tx] + pb * xm2 + pt * xv;
+                const T d = pw + pe + ps + pn + pb + pt;
+                r = fm1 - (d * xm1 - nb);
+            }
+            const T p = r + __shfl_down(r, 1, 64);  // x pairs: lanes (l, l+1) of one 32-lane row
+            if ((s & 1) == 0) {
+                part = p;  // even plane of the pair
+            } else {
+                const T p2 = part + p;
+                sr[ty][tx] = p2;
+                lds_barrier();
+                if (own && (tx & 1) && (ty & 1))
+                    rc[cell(cnx, cny, i >> 1, j >> 1, (k0 - 2 + s) >> 1)] = p2 + sr[ty + 1][tx];
+            }
+        }
+        xm2 = xm1;
+        xm1 = xv;
+        fm1 = a.f;
+        pw = st.ww;
+        pe = st.we;
+        ps = st.ws;
+        pn = st.wn;
+        pb = st.wb;
+        pt = st.wt;
+        ++s;
+    }
+};
+
 // ---------------------------------------------------------------- kernels
 
 template <class T, int BX, bool RHO>
@@ -422,6 +517,18 @@ __global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_residual_restrict(L
     OpRestrict<T, BX> op{f, x, rc, L.nx >> 1, L.ny >> 1, bz * kper, T(0)};
     double acc[1] = {0.0};
     march<T, BX, RHO>(L, kper, xcd, op, acc);
+}
+
+template <class T, bool RHO>
+__global__ void __launch_bounds__(kOvlX * kOvlY) m_first_restrict(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x,
+                                                                 T* __restrict__ rc, int kper, int xcd, T omega)
+{
+    int bx, by, bz;
+    tile_of_block(bx, by, bz, xcd);
+    const int k0 = bz * kper;
+    OpFirstRestrict<T> op{f, L.invd, x, rc, omega, L.nx >> 1, L.ny >> 1, k0, min(L.nz, k0 + kper) - k0};
+    double acc[1] = {0.0};
+    march<T, kOvlX, RHO, true, kOvlX * kOvlY>(L, kper, xcd, op, acc);
 }
 
 template <class T, int BX, bool RHO>

@@ -106,6 +106,20 @@ static MGeo mgeo(int nx, int ny, int nz, int bx_max, bool even_k = false, int ma
     return {dim3(gx, gy, gz), dim3(bx, by, 1), kper, bx};
 }
 
+// Geometry of an overlapped-tile launch (m_first_restrict): tiles of
+// (kOvlX - 2) x (kOvlY - 2) own cells, z split into an even number of planes
+// per block so that plane pairs stay in one block.  nz is even.
+static MGeo ovl_geo(int nx, int ny, int nz, int max_blocks)
+{
+    const int gx = (nx + kOvlX - 3) / (kOvlX - 2), gy = (ny + kOvlY - 3) / (kOvlY - 2);
+    const int tiles = gx * gy;
+    int gz = std::max(1, std::min(nz / 2, max_blocks / std::max(1, tiles)));
+    int kper = (nz + gz - 1) / gz;
+    if (kper & 1) ++kper;
+    gz = (nz + kper - 1) / kper;
+    return {dim3(gx, gy, gz), dim3(kOvlX, kOvlY, 1), kper, kOvlX};
+}
+
 template <int B>
 using BxC = std::integral_constant<int, B>;
 
@@ -205,6 +219,10 @@ struct Params {
     int tail_max = 1024;        // largest level the one-launch cycle starts on (at most kTailMaxCells)
     double wc = 2.0;
     bool graphs = true;
+    int fuse = 1;               // one-sweep levels: first sweep and restriction in one launch on
+                                // float32 levels (1), on every level (2) or nowhere (0); measured
+                                // faster in float32 only (the float64 launch holds fewer waves)
+    int oblocks = 3072;         // block budget of the fused launch
     double omega = 1.0;         // SOR factor of the red-black smoother
     bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
     bool march = true;          // plane-marching stencil kernels (else one thread per cell column)
@@ -277,10 +295,10 @@ struct Handle {
 // Kernel identities for timing (finest level; float32 and float64 variants apart).
 enum KId : int {
     KT_SMOOTH_FIRST = 0, KT_SMOOTH_HALF, KT_SMOOTH_HALF_DOT, KT_RESTRICT, KT_PROLONG_BLACK, KT_DIR_APPLY,
-    KT_UPDATE_XR, KT_TRUE_RESIDUAL, KT_N
+    KT_UPDATE_XR, KT_TRUE_RESIDUAL, KT_FIRST_RESTRICT, KT_N
 };
 static const char* kt_name[KT_N] = {"smooth_first", "smooth_half", "smooth_half_dots", "residual_restrict",
-                                    "prolong_black", "dir_apply", "update_xr", "true_residual"};
+                                    "prolong_black", "dir_apply", "update_xr", "true_residual", "first_restrict"};
 
 static hipEvent_t take_event(Handle* H)
 {
@@ -698,6 +716,19 @@ static void launch_restrict(Handle* H, const LevelView<T>& v, const T* f, const 
     check_launch();
 }
 
+// First sweep from zero and restriction of its residual in one launch (a
+// level smoothed once before the coarse correction).
+template <class T>
+static void launch_first_restrict(Handle* H, const LevelView<T>& v, const T* f, T* x, T* rc)
+{
+    const MGeo g = ovl_geo(v.nx, v.ny, v.nz, H->prm.oblocks);
+    with_rho(v, [&](auto R) {
+        m_first_restrict<T, decltype(R)::value>
+            <<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper, xcd_of(H, v), (T)H->prm.omega);
+    });
+    check_launch();
+}
+
 template <class T>
 static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, const T* x, const T* e, T wc, T* y)
 {
@@ -810,17 +841,21 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
                : (V.kcyc && l >= 2 && H->prm.nuk2 > 0)                 ? H->prm.nuk2
                : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0)        ? H->prm.nuv
                                                                        : H->prm.nuc;
-    {
-        // reads f, 1/D and the weights (or the density); writes x
-        TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
-        launch_first<T>(H, V.v, f, V.c);
-    }
-    for (int s = 1; s < nu; ++s) {
-        smooth_half(H, V, fine, f, V.c, 0, 0, (const T*)nullptr, l);
-        smooth_half(H, V, fine, f, V.c, 1, 0, (const T*)nullptr, l);
-    }
     Lev<T>& C = Hh.L[l + 1];
-    {
+    if (nu == 1 && H->prm.march && (H->prm.fuse == 2 || (H->prm.fuse == 1 && sizeof(T) == 4))) {
+        // reads f, 1/D and the weights (or the density); writes x and the coarse right-hand side
+        TimeScope ts(H, fine ? kid<T>(KT_FIRST_RESTRICT) : -1, (double)V.n * sizeof(T) * (3.125 + weight_arrays(H, V.v)));
+        launch_first_restrict<T>(H, V.v, f, V.c, C.rhs);
+    } else {
+        {
+            // reads f, 1/D and the weights (or the density); writes x
+            TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
+            launch_first<T>(H, V.v, f, V.c);
+        }
+        for (int s = 1; s < nu; ++s) {
+            smooth_half(H, V, fine, f, V.c, 0, 0, (const T*)nullptr, l);
+            smooth_half(H, V, fine, f, V.c, 1, 0, (const T*)nullptr, l);
+        }
         // reads x, f and the weights (or the density); writes the coarse right-hand side
         TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (2.125 + weight_arrays(H, V.v)));
         launch_restrict<T>(H, V.v, f, V.c, C.rhs);
@@ -1203,6 +1238,8 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
+    if (const char* s = getenv("PP_FUSE")) p.fuse = std::max(0, std::min(2, atoi(s)));
+    if (const char* s = getenv("PP_OBLOCKS")) p.oblocks = std::max(8, std::min(1 << 16, atoi(s)));
     if (const char* s = getenv("PP_TAIL")) p.tail = atoi(s) != 0;
     if (const char* s = getenv("PP_TAILMAX")) p.tail_max = std::max(2, std::min(kTailMaxCells, atoi(s)));
     if (const char* s = getenv("PP_OMEGA")) p.omega = atof(s);
