@@ -486,6 +486,76 @@ struct OpFirstRestrict {
     }
 };
 
+// Prolongation with the black update (as OpProlongBlack) and the red half-sweep
+// after it (as OpHalf with colour 0) in one pass, for a level smoothed once
+// after the coarse correction.  The red update needs the new black values around
+// it and those need the prolongated red values around them, so the march runs
+// with overlapped tiles (OVL) and the red update trails the black one by a plane,
+// as in OpFirstRestrict.  Writes z = y on black cells and the updated red cells;
+// dots sum(z) and <z, q> over the block's own cells.
+template <class T, int NDOT, class TQ>
+struct OpProlongHalf {
+    const T *f, *x, *e;
+    const TQ* q;
+    T* z;
+    T wc, omega;
+    int cnx, cny;
+    int s = 0;  // step: plane k0 - 1 + s
+    T ym2 = T(0), ym1 = T(0), fm1 = T(0);  // y two and one planes back, f one back
+    TQ qm1 = TQ(0);
+    int cm1 = 0, km1 = 0;                  // cell index and plane one back
+    T pw = T(0), pe = T(0), ps = T(0), pn = T(0), pb = T(0), pt = T(0);
+    struct Raw { T x, e; };
+    struct Ex { T f; TQ q; };
+    __device__ Raw load(int c, int i, int j, int k) const { return {x[c], e[cell(cnx, cny, i >> 1, j >> 1, k >> 1)]}; }
+    __device__ T val(const Raw& a) const { return a.x + wc * a.e; }
+    __device__ Ex extra(int c) const { return {f[c], NDOT >= 2 ? q[c] : TQ(0)}; }
+    template <class A>
+    __device__ void apply(int c, int i, int j, int k, T vc, const Raw&, const Ex& ex, const Stencil<T>& st, A& acc, bool act)
+    {
+        __shared__ T sy[2][kOvlY][kOvlX];  // y of the last two planes
+        const int tx = threadIdx.x, ty = threadIdx.y;
+        T yv = T(0);
+        if (act) {
+            if (((i + j + k) & 1) == 0) {
+                yv = vc;
+            } else {
+                yv = gs_value(st.s, ex.f, st.d);
+                if (omega != T(1)) yv = vc + omega * (yv - vc);
+            }
+        }
+        const bool own = act && tx >= 1 && tx <= kOvlX - 2 && ty >= 1 && ty <= kOvlY - 2;
+        sy[s & 1][ty][tx] = yv;  // read at the next step, after its barrier
+        if (s >= 2 && own) {
+            // plane km1 (a real plane of the block): red cells relaxed from y of three planes
+            T zv = ym1;
+            if (((i + j + km1) & 1) == 0) {
+                const int b = (s - 1) & 1;
+                const T nb = pw * sy[b][ty][tx - 1] + pe * sy[b][ty][tx + 1] + ps * sy[b][ty - 1][tx] +
+                             pn * sy[b][ty + 1][tx] + pb * ym2 + pt * yv;
+                zv = gs_value(nb, fm1, pw + pe + ps + pn + pb + pt);
+                if (omega != T(1)) zv = ym1 + omega * (zv - ym1);
+            }
+            z[cm1] = zv;
+            if constexpr (NDOT >= 1) acc[0] += (double)zv;
+            if constexpr (NDOT >= 2) acc[1] += (double)zv * (double)qm1;
+        }
+        ym2 = ym1;
+        ym1 = yv;
+        fm1 = ex.f;
+        qm1 = ex.q;
+        cm1 = c;
+        km1 = k;
+        pw = st.ww;
+        pe = st.we;
+        ps = st.ws;
+        pn = st.wn;
+        pb = st.wb;
+        pt = st.wt;
+        ++s;
+    }
+};
+
 // ---------------------------------------------------------------- kernels
 
 template <class T, int BX, bool RHO>
@@ -529,6 +599,18 @@ __global__ void __launch_bounds__(kOvlX * kOvlY) m_first_restrict(LevelView<T> L
     OpFirstRestrict<T> op{f, L.invd, x, rc, omega, L.nx >> 1, L.ny >> 1, k0, min(L.nz, k0 + kper) - k0};
     double acc[1] = {0.0};
     march<T, kOvlX, RHO, true, kOvlX * kOvlY>(L, kper, xcd, op, acc);
+}
+
+template <class T, bool RHO, int NDOT, class TQ>
+__global__ void __launch_bounds__(kOvlX * kOvlY) m_prolong_half(LevelView<T> L, const T* __restrict__ f,
+                                                               const T* __restrict__ x, const T* __restrict__ e, T wc,
+                                                               T* __restrict__ z, const TQ* __restrict__ q, Reduce R,
+                                                               int kper, int xcd, T omega)
+{
+    OpProlongHalf<T, NDOT, TQ> op{f, x, e, q, z, wc, omega, L.nx >> 1, L.ny >> 1};
+    double acc[NDOT > 0 ? NDOT : 1] = {};
+    march<T, kOvlX, RHO, true, kOvlX * kOvlY>(L, kper, xcd, op, acc);
+    if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
 }
 
 template <class T, int BX, bool RHO>

@@ -219,10 +219,16 @@ struct Params {
     int tail_max = 1024;        // largest level the one-launch cycle starts on (at most kTailMaxCells)
     double wc = 2.0;
     bool graphs = true;
-    int fuse = 1;               // one-sweep levels: first sweep and restriction in one launch on
-                                // float32 levels (1), on every level (2) or nowhere (0); measured
-                                // faster in float32 only (the float64 launch holds fewer waves)
-    int oblocks = 3072;         // block budget of the fused launch
+    int fuse = 1;               // levels smoothed once: first sweep with restriction, and
+                                // prolongation with the last half-sweep, as overlapped-tile
+                                // launches on float32 levels (1), on every level (2) or nowhere
+                                // (0); measured faster in float32 only (the float64 launches
+                                // hold fewer waves per CU)
+    int oblocks = 3072;         // block budget of an overlapped-tile launch
+    int pfuse = 1;              // fuse the post-smoothing too (the pre-smoothing always when fused)
+    long fbig = 1L << 20;       // fused launches on levels with at least fbig cells (the ring and the
+    long fsmall = 65536;        // two extra planes cost little) or at most fsmall (bound by launch
+                                // latency); between them the overlap costs more than it saves
     double omega = 1.0;         // SOR factor of the red-black smoother
     bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
     bool march = true;          // plane-marching stencil kernels (else one thread per cell column)
@@ -230,6 +236,8 @@ struct Params {
     int mblocks = 768;          // blocks of a 256-thread march launch (at most; z split to reach it)
     int fblocks = 512;          // blocks of a 512-thread (finest-level float64) march launch
     int xcd = 2;                // XCD-aware tile order: 0 never, 1 always, 2 below the finest level
+    int oxcd = 1;               // the same for the overlapped-tile launches (-1: as xcd); their
+                                // ring rows then come from the L2 of the XCD, measured 3 % faster
     bool rho = true;            // finest-level march kernels form the weights from the density
 };
 
@@ -295,10 +303,11 @@ struct Handle {
 // Kernel identities for timing (finest level; float32 and float64 variants apart).
 enum KId : int {
     KT_SMOOTH_FIRST = 0, KT_SMOOTH_HALF, KT_SMOOTH_HALF_DOT, KT_RESTRICT, KT_PROLONG_BLACK, KT_DIR_APPLY,
-    KT_UPDATE_XR, KT_TRUE_RESIDUAL, KT_FIRST_RESTRICT, KT_N
+    KT_UPDATE_XR, KT_TRUE_RESIDUAL, KT_FIRST_RESTRICT, KT_PROLONG_HALF, KT_N
 };
 static const char* kt_name[KT_N] = {"smooth_first", "smooth_half", "smooth_half_dots", "residual_restrict",
-                                    "prolong_black", "dir_apply", "update_xr", "true_residual", "first_restrict"};
+                                    "prolong_black", "dir_apply", "update_xr", "true_residual", "first_restrict",
+                                    "prolong_half"};
 
 static hipEvent_t take_event(Handle* H)
 {
@@ -387,6 +396,8 @@ static bool valid_cfg(const pp_config* cfg, std::string* why)
             MGeo m = mgeo(cfg->nx, cfg->ny, cfg->nz, b);
             most = std::max(most, (size_t)m.grid.x * m.grid.y * m.grid.z);
         }
+        const MGeo o = ovl_geo(cfg->nx, cfg->ny, cfg->nz, kMaxRedBlocks);  // a reducing overlapped launch
+        most = std::max(most, (size_t)o.grid.x * o.grid.y * o.grid.z);
         if (most > (size_t)kMaxRedBlocks) {
             if (why) *why = "cross-section too large (more than 2048 thread tiles per plane)";
             return false;
@@ -623,6 +634,13 @@ static double weight_arrays(const Handle* H, const LevelView<T>& v)
     return (v.rho && H->prm.march) ? 1.0 : 3.0;
 }
 
+// Whether a level smoothed once runs its passes as overlapped-tile launches.
+static bool fused(const Handle* H, size_t prec, size_t n)
+{
+    return H->prm.march && ((long)n >= H->prm.fbig || (long)n <= H->prm.fsmall) &&
+           (H->prm.fuse == 2 || (H->prm.fuse == 1 && prec == 4));
+}
+
 // 1/D arrays read by a half-sweep or prolongation: the march kernels divide by
 // the stencil's own diagonal, the per-cell kernels read 1/D.
 static double invd_arrays(const Handle* H) { return H->prm.march ? 0.0 : 1.0; }
@@ -722,11 +740,31 @@ template <class T>
 static void launch_first_restrict(Handle* H, const LevelView<T>& v, const T* f, T* x, T* rc)
 {
     const MGeo g = ovl_geo(v.nx, v.ny, v.nz, H->prm.oblocks);
+    const int xcd = H->prm.oxcd < 0 ? xcd_of(H, v) : H->prm.oxcd;
     with_rho(v, [&](auto R) {
         m_first_restrict<T, decltype(R)::value>
-            <<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper, xcd_of(H, v), (T)H->prm.omega);
+            <<<g.grid, g.block, 0, H->stream>>>(v, f, x, rc, g.kper, xcd, (T)H->prm.omega);
     });
     check_launch();
+}
+
+// Prolongation, black update and the red half-sweep after it in one launch (a
+// level smoothed once after the coarse correction); NDOT dots as in launch_half.
+template <class T, int NDOT, class TQ>
+static dim3 launch_prolong_half(Handle* H, const LevelView<T>& v, const T* f, const T* x, const T* e, T wc, T* z,
+                                const TQ* q, const Reduce& R)
+{
+    // a reducing launch writes one partial per block: at most kMaxRedBlocks blocks
+    const MGeo g = ovl_geo(v.nx, v.ny, v.nz, NDOT > 0 ? std::min(H->prm.oblocks, kMaxRedBlocks) : H->prm.oblocks);
+    if (NDOT > 0 && (size_t)g.grid.x * g.grid.y * g.grid.z > (size_t)kMaxRedBlocks)
+        throw Fail(PP_ERR_INVALID, "cross-section too large for a reducing overlapped-tile launch");
+    const int xcd = H->prm.oxcd < 0 ? xcd_of(H, v) : H->prm.oxcd;
+    with_rho(v, [&](auto W) {
+        m_prolong_half<T, decltype(W)::value, NDOT, TQ>
+            <<<g.grid, g.block, 0, H->stream>>>(v, f, x, e, wc, z, q, R, g.kper, xcd, (T)H->prm.omega);
+    });
+    check_launch();
+    return g.grid;
 }
 
 template <class T>
@@ -842,7 +880,7 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
                : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0)        ? H->prm.nuv
                                                                        : H->prm.nuc;
     Lev<T>& C = Hh.L[l + 1];
-    if (nu == 1 && H->prm.march && (H->prm.fuse == 2 || (H->prm.fuse == 1 && sizeof(T) == 4))) {
+    if (nu == 1 && fused(H, sizeof(T), V.n)) {
         // reads f, 1/D and the weights (or the density); writes x and the coarse right-hand side
         TimeScope ts(H, fine ? kid<T>(KT_FIRST_RESTRICT) : -1, (double)V.n * sizeof(T) * (3.125 + weight_arrays(H, V.v)));
         launch_first_restrict<T>(H, V.v, f, V.c, C.rhs);
@@ -868,6 +906,21 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     } else {
         e = mgcycle(H, Hh, l + 1, C.rhs, 0, (const T*)nullptr);
         wc = (T)H->prm.wc;
+    }
+    if (nu == 1 && H->prm.pfuse && fused(H, sizeof(T), V.n)) {
+        // reads x, f, the weights (or the density), the coarse correction and q for the dot;
+        // writes z
+        const Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
+        dim3 grid;
+        {
+            TimeScope ts(H, fine ? kid<T>(KT_PROLONG_HALF) : -1,
+                         (double)V.n * ((3.125 + weight_arrays(H, V.v)) * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
+            if (ndot == 0) grid = launch_prolong_half<T, 0, TQ>(H, V.v, f, V.c, e, wc, V.c2, q, R);
+            else if (ndot == 1) grid = launch_prolong_half<T, 1, TQ>(H, V.v, f, V.c, e, wc, V.c2, q, R);
+            else grid = launch_prolong_half<T, 2, TQ>(H, V.v, f, V.c, e, wc, V.c2, q, R);
+        }
+        if (ndot > 0) finish(H, R, grid, ndot);
+        return V.c2;
     }
     {
         // reads x, f, the weights (or the density) and the coarse correction (the per-cell
@@ -1239,6 +1292,9 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
     if (const char* s = getenv("PP_FUSE")) p.fuse = std::max(0, std::min(2, atoi(s)));
+    if (const char* s = getenv("PP_PFUSE")) p.pfuse = atoi(s) != 0;
+    if (const char* s = getenv("PP_FBIG")) p.fbig = std::max(0L, atol(s));
+    if (const char* s = getenv("PP_FSMALL")) p.fsmall = std::max(0L, atol(s));
     if (const char* s = getenv("PP_OBLOCKS")) p.oblocks = std::max(8, std::min(1 << 16, atoi(s)));
     if (const char* s = getenv("PP_TAIL")) p.tail = atoi(s) != 0;
     if (const char* s = getenv("PP_TAILMAX")) p.tail_max = std::max(2, std::min(kTailMaxCells, atoi(s)));
@@ -1249,6 +1305,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NUK2")) p.nuk2 = std::max(0, atoi(s));
     if (const char* s = getenv("PP_MARCH")) p.march = atoi(s) != 0;
     if (const char* s = getenv("PP_XCD")) p.xcd = atoi(s);
+    if (const char* s = getenv("PP_OXCD")) p.oxcd = atoi(s);
     if (const char* s = getenv("PP_RHO")) p.rho = atoi(s) != 0;
     if (const char* s = getenv("PP_FBLOCKS")) p.fblocks = std::max(32, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBLOCKS")) p.mblocks = std::max(64, std::min(kMaxRedBlocks, atoi(s)));
