@@ -303,6 +303,42 @@ __device__ inline void tail_restrict(const A& a, T* fc, int cnx, int cny, int cn
     __syncthreads();
 }
 
+// The same for a level of at most kTailThreads cells: every thread forms one
+// cell's residual into rbuf, then each coarse cell adds its 8 children in the
+// order tail_restrict_cell does (the same sums, without its serial chain).
+template <class T, class A>
+__device__ inline void tail_restrict_wide(const A& a, T* rbuf, T* fc, int cnx, int cny, int cn)
+{
+    const int n = a.nx * a.ny * a.nz;
+    const float inv_nx = 1.0f / (float)a.nx, inv_ny = 1.0f / (float)a.ny;
+    for (int c = threadIdx.x; c < n; c += kTailThreads) {
+        const int row = qdiv(c, a.nx, inv_nx);
+        const int i = c - row * a.nx;
+        const int k = qdiv(row, a.ny, inv_ny);
+        const int j = row - k * a.ny;
+        T s, d;
+        tail_stencil<T>(a, c, nb_flags(i, j, k, a.nx, a.ny, a.nz), s, d);
+        rbuf[c] = a.f(c) - (d * a.x(c) - s);
+    }
+    __syncthreads();
+    const float inv_cx = 1.0f / (float)cnx, inv_cy = 1.0f / (float)cny;
+    for (int cc = threadIdx.x; cc < cn; cc += kTailThreads) {
+        const int row = qdiv(cc, cnx, inv_cx);
+        const int I = cc - row * cnx;
+        const int K = qdiv(row, cny, inv_cy);
+        const int J = row - K * cny;
+        T acc = T(0);
+#pragma unroll
+        for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+                for (int di = 0; di < 2; ++di) acc += rbuf[cell(a.nx, a.ny, 2 * I + di, 2 * J + dj, 2 * K + dk)];
+        fc[cc] = acc;
+    }
+    __syncthreads();
+}
+
 // x += wc * e(parent) on every cell of a later level (nx even).
 template <class T>
 __device__ inline void tail_prolong_small(const TailS<T>& a, const T* e, T wc)
@@ -339,6 +375,22 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
     const int last = D.nlev - 1;
     const T om = D.omega;
     const TailLevel<T>& V0 = D.L[0];
+
+    // the dense inverse's entries this thread multiplies on the last level (see
+    // below); in float32 they are loaded now, so that their latency overlaps the
+    // cycle (in float64 they would not fit in registers beside it)
+    constexpr int kPer = kTailDenseMax / kTailDenseSplit;
+    constexpr bool kEarly = sizeof(T) == 4;
+    const int dr = threadIdx.x % kTailDenseMax, dc0 = (threadIdx.x / kTailDenseMax) * kPer;
+    T m[kPer];
+    auto load_m = [&]() {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int c = dc0 + u;
+            m[u] = (dr < D.nd && c < D.nd) ? ldg(D.Minv, c * D.nd + dr) : T(0);
+        }
+    };
+    if constexpr (kEarly) load_m();
 
     // stage the operators of the later levels (and, with LDS0, the first level's
     // operator and right-hand side after them): every load of the cycle but the
@@ -389,7 +441,8 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
         tail_half_first(g, pinfo, np0, 0, om);
         tail_half_first(g, pinfo, np0, 1, om);
     }
-    tail_restrict<T>(g, sf + D.L[1].off, D.L[1].v.nx, D.L[1].v.ny, D.L[1].n);
+    if (V0.n <= kTailThreads) tail_restrict_wide<T>(g, dpart, sf + D.L[1].off, D.L[1].v.nx, D.L[1].v.ny, D.L[1].n);
+    else tail_restrict<T>(g, sf + D.L[1].off, D.L[1].v.nx, D.L[1].v.ny, D.L[1].n);
 
     // later levels down to the last
     for (int l = 1; l < last; ++l) {
@@ -422,19 +475,12 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
             // x = Minv f (nd <= kTailDenseMax): thread t forms row t mod kTailDenseMax
             // over one chunk of the columns, with all of its loads issued together;
             // the chunks are then added in a fixed order
-            constexpr int kPer = kTailDenseMax / kTailDenseSplit;
             const int nd = D.nd;
-            const int r = threadIdx.x % kTailDenseMax, c0 = (threadIdx.x / kTailDenseMax) * kPer;
-            T m[kPer];
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int c = c0 + u;
-                m[u] = (r < nd && c < nd) ? ldg(D.Minv, c * nd + r) : T(0);
-            }
+            if constexpr (!kEarly) load_m();
             T acc = T(0);
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
-                const int c = c0 + u;
+                const int c = dc0 + u;
                 acc += m[u] * (c < nd ? b.sf[c] : T(0));
             }
             dpart[threadIdx.x] = acc;
