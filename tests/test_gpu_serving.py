@@ -116,3 +116,28 @@ def test_poisson_replay_and_warm_resident_case(items):
         assert r2["status"] == 0 and not r2["new_density"]
         assert r2["stats"]["iters"] == 0
         assert P.relative_linf_error(again.cpu().numpy(), it["alone"]) < 1e-12
+
+
+def test_allocation_failure_is_reported(items, monkeypatch):
+    """A device allocation failure at handle creation, forced from the host through
+    PP_FAULT_OOM_AT (read when a handle is made), is an error status for the binding
+    and for a serving request, and leaves nothing behind: the same request succeeds
+    once the switch is gone."""
+    it = items[0]
+    c = it["case"]
+    monkeypatch.setenv("PP_FAULT_OOM_AT", "1")
+    with pytest.raises(ppsolve.PPError) as e:
+        ppsolve.Solver(c.nx, c.ny, c.nz, c.h, mode="fp32_refined", tol=TOL)
+    assert e.value.code == ppsolve.PP_ERR_OOM
+    out = torch.zeros_like(it["rhs_t"])
+    with serve.Server(64 << 30, slots=2) as srv:
+        r = srv.wait(srv.submit(300, it["cfg"], vp(it["rho_t"]), vp(it["rhs_t"]), vp(out)))
+        say("   forced failure", r["status"], r["message"])
+        assert r["status"] == ppsolve.PP_ERR_OOM and "injected" in r["message"]
+        monkeypatch.delenv("PP_FAULT_OOM_AT")
+        r = srv.wait(srv.submit(300, it["cfg"], vp(it["rho_t"]), vp(it["rhs_t"]), vp(out)))
+        st = srv.stats()
+    say("   stats", st)
+    assert r["status"] == 0
+    assert st["rejected"] == 1 and st["succeeded"] == 1
+    np.testing.assert_array_equal(out.cpu().numpy(), it["alone"])
