@@ -24,6 +24,7 @@
 // block to finish sums all partials in a fixed order.  Results therefore do
 // not depend on scheduling (bitwise repeatable).
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -43,6 +44,11 @@ struct LevelView {
     const T* wz;    // +z face weight (the last plane's face joins plane 0)
     const T* invd;  // 1 / D_c
     const T* rho = nullptr;  // finest level: density, from which the plane-marching kernels derive the weights
+    // float16 copies of wx, wy, wz that the plane-marching kernels read instead
+    // (coarse levels of the float32 preconditioner), or null
+    const __half* hwx = nullptr;
+    const __half* hwy = nullptr;
+    const __half* hwz = nullptr;
 };
 
 // Reduction target: per-block partials and the output slots.  A reducing
@@ -474,12 +480,14 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(int nx, int ny, int nz, cons
     }
 }
 
-// 1/D of a level plus float32 copies of its weights (when the float32 arrays exist).
+// 1/D of a level plus float32 copies of its weights (when the float32 arrays
+// exist) and float16 copies (when those exist).
 __global__ void __launch_bounds__(kBlock) k_level_finish(int nx, int ny, int nz, const double* __restrict__ wx,
                                                         const double* __restrict__ wy, const double* __restrict__ wz,
                                                         double* __restrict__ invd64, float* __restrict__ wx32,
                                                         float* __restrict__ wy32, float* __restrict__ wz32,
-                                                        float* __restrict__ invd32, int kper)
+                                                        float* __restrict__ invd32, __half* __restrict__ wx16,
+                                                        __half* __restrict__ wy16, __half* __restrict__ wz16, int kper)
 {
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
@@ -495,6 +503,11 @@ __global__ void __launch_bounds__(kBlock) k_level_finish(int nx, int ny, int nz,
             wy32[c] = (float)wy[c];
             wz32[c] = (float)wz[c];
             invd32[c] = (float)inv;
+        }
+        if (wx16) {
+            wx16[c] = __float2half((float)wx[c]);
+            wy16[c] = __float2half((float)wy[c]);
+            wz16[c] = __float2half((float)wz[c]);
         }
     }
 }

@@ -71,6 +71,12 @@ __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_b
 template <class T, bool RHO>
 constexpr int kMarchThreads = (RHO && sizeof(T) == 8) ? 512 : kBlock;
 
+// Where a march kernel's face weights come from (its WM parameter): the level's
+// stored arrays in the kernel's precision, the density (finest level), or
+// float16 copies of the stored weights (coarse levels of the float32
+// preconditioner: 6 bytes per cell instead of 12).
+enum : int { kWStored = 0, kWRho = 1, kWHalf = 2 };
+
 // Register sets of plane loads (loads are issued kMarchSets - 1 planes ahead
 // of the plane being computed).
 constexpr int kMarchSets = 2;
@@ -107,9 +113,10 @@ __device__ inline float gs_value(float s, float f, float d) { return (s + f) * _
 // the neighbouring blocks, and the march runs one plane below and one above
 // the block's z range (periodic in z).  apply then sees ring cells and the two
 // extra planes as well; cells outside the grid have act false.
-template <class T, int BX, bool RHO, bool OVL = false, int NT = kMarchThreads<T, RHO>, class Op, class Acc>
+template <class T, int BX, int WM, bool OVL = false, int NT = kMarchThreads<T, WM == kWRho>, class Op, class Acc>
 __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, Acc& acc)
 {
+    constexpr bool RHO = WM == kWRho, HALF = WM == kWHalf;
     using Raw = typename Op::Raw;
     using Ex = typename Op::Ex;
     using Regs = PlaneRegs<T, Raw, Ex>;
@@ -152,6 +159,12 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
             S.wz = L.rho[c + (kt - k) * sz];
             S.wxh = L.rho[c + oi];
             S.wyh = L.rho[c + oj * sy];
+        } else if constexpr (HALF) {
+            S.wx = (T)__half2float(L.hwx[c]);
+            S.wy = (T)__half2float(L.hwy[c]);
+            S.wz = (T)__half2float(L.hwz[c]);
+            S.wxh = (T)__half2float(L.hwx[c + owx]);
+            S.wyh = (T)__half2float(L.hwy[c + owy]);
         } else {
             S.wx = L.wx[c];
             S.wy = L.wy[c];
@@ -175,6 +188,8 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
     if constexpr (RHO) {
         rho_c = L.rho[c];
         wzb = face_beta(L.rho[c + (kb0 - ks) * sz], rho_c);
+    } else if constexpr (HALF) {
+        wzb = (T)__half2float(L.hwz[c + (kb0 - ks) * sz]);
     } else {
         wzb = L.wz[c + (kb0 - ks) * sz];
     }
@@ -558,27 +573,27 @@ struct OpProlongHalf {
 
 // ---------------------------------------------------------------- kernels
 
-template <class T, int BX, bool RHO>
-__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
+template <class T, int BX, int WM>
+__global__ void __launch_bounds__((kMarchThreads<T, WM == kWRho>)) m_smooth_first(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x, int kper,
                                                         int xcd, T omega)
 {
     OpFirst<T> op{f, L.invd, x, omega};
     double acc[1] = {0.0};
-    march<T, BX, RHO>(L, kper, xcd, op, acc);
+    march<T, BX, WM>(L, kper, xcd, op, acc);
 }
 
-template <class T, int BX, bool RHO, int NDOT, class TQ>
-__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
+template <class T, int BX, int WM, int NDOT, class TQ>
+__global__ void __launch_bounds__((kMarchThreads<T, WM == kWRho>)) m_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
                                                        int xcd, const TQ* __restrict__ q, Reduce R, T omega)
 {
     OpHalf<T, NDOT, TQ> op{f, x, q, colour, omega};
     double acc[NDOT > 0 ? NDOT : 1] = {};
-    march<T, BX, RHO>(L, kper, xcd, op, acc);
+    march<T, BX, WM>(L, kper, xcd, op, acc);
     if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
 }
 
-template <class T, int BX, bool RHO>
-__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
+template <class T, int BX, int WM>
+__global__ void __launch_bounds__((kMarchThreads<T, WM == kWRho>)) m_residual_restrict(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                              T* __restrict__ rc, int kper, int xcd)
 {
     static_assert(BX <= 32, "the 2x2 sum pairs rows within one wavefront");
@@ -586,10 +601,10 @@ __global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_residual_restrict(L
     tile_of_block(bx, by, bz, xcd);
     OpRestrict<T, BX> op{f, x, rc, L.nx >> 1, L.ny >> 1, bz * kper, T(0)};
     double acc[1] = {0.0};
-    march<T, BX, RHO>(L, kper, xcd, op, acc);
+    march<T, BX, WM>(L, kper, xcd, op, acc);
 }
 
-template <class T, bool RHO>
+template <class T, int WM>
 __global__ void __launch_bounds__(kOvlX * kOvlY) m_first_restrict(LevelView<T> L, const T* __restrict__ f, T* __restrict__ x,
                                                                  T* __restrict__ rc, int kper, int xcd, T omega)
 {
@@ -598,10 +613,10 @@ __global__ void __launch_bounds__(kOvlX * kOvlY) m_first_restrict(LevelView<T> L
     const int k0 = bz * kper;
     OpFirstRestrict<T> op{f, L.invd, x, rc, omega, L.nx >> 1, L.ny >> 1, k0, min(L.nz, k0 + kper) - k0};
     double acc[1] = {0.0};
-    march<T, kOvlX, RHO, true, kOvlX * kOvlY>(L, kper, xcd, op, acc);
+    march<T, kOvlX, WM, true, kOvlX * kOvlY>(L, kper, xcd, op, acc);
 }
 
-template <class T, bool RHO, int NDOT, class TQ>
+template <class T, int WM, int NDOT, class TQ>
 __global__ void __launch_bounds__(kOvlX * kOvlY) m_prolong_half(LevelView<T> L, const T* __restrict__ f,
                                                                const T* __restrict__ x, const T* __restrict__ e, T wc,
                                                                T* __restrict__ z, const TQ* __restrict__ q, Reduce R,
@@ -609,22 +624,22 @@ __global__ void __launch_bounds__(kOvlX * kOvlY) m_prolong_half(LevelView<T> L, 
 {
     OpProlongHalf<T, NDOT, TQ> op{f, x, e, q, z, wc, omega, L.nx >> 1, L.ny >> 1};
     double acc[NDOT > 0 ? NDOT : 1] = {};
-    march<T, kOvlX, RHO, true, kOvlX * kOvlY>(L, kper, xcd, op, acc);
+    march<T, kOvlX, WM, true, kOvlX * kOvlY>(L, kper, xcd, op, acc);
     if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
 }
 
-template <class T, int BX, bool RHO>
-__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
+template <class T, int BX, int WM>
+__global__ void __launch_bounds__((kMarchThreads<T, WM == kWRho>)) m_prolong_black(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
                                                          const T* __restrict__ e, T wc, T* __restrict__ y, int kper, int xcd,
                                                          T omega)
 {
     OpProlongBlack<T> op{f, x, e, y, wc, omega, L.nx >> 1, L.ny >> 1};
     double acc[1] = {0.0};
-    march<T, BX, RHO>(L, kper, xcd, op, acc);
+    march<T, BX, WM>(L, kper, xcd, op, acc);
 }
 
-template <class T, int BX, bool RHO, class TZ, bool BETA, bool FINE>
-__global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
+template <class T, int BX, int WM, class TZ, bool BETA, bool FINE>
+__global__ void __launch_bounds__((kMarchThreads<T, WM == kWRho>)) m_dir_apply(LevelView<T> L, const TZ* __restrict__ z, const T* __restrict__ dold,
                                                      T* __restrict__ dnew, T* __restrict__ q, const T* __restrict__ r,
                                                      T* __restrict__ x, Coefs beta, Coefs mean, int use_mean, Coefs aprev,
                                                      int kper, int xcd, Reduce R)
@@ -632,18 +647,18 @@ __global__ void __launch_bounds__((kMarchThreads<T, RHO>)) m_dir_apply(LevelView
     OpDir<T, TZ, BETA, FINE> op{z, dold, r, dnew, q, x, BETA ? (T)beta.get() : T(0), use_mean ? (T)mean.get() : T(0),
                                 (FINE && BETA) ? (T)aprev.get() : T(0)};
     double acc[2] = {0.0, 0.0};
-    march<T, BX, RHO>(L, kper, xcd, op, acc);
+    march<T, BX, WM>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 
-template <int BX, bool RHO>
-__global__ void __launch_bounds__((kMarchThreads<double, RHO>)) m_true_residual(LevelView<double> L, const double* __restrict__ f,
+template <int BX, int WM>
+__global__ void __launch_bounds__((kMarchThreads<double, WM == kWRho>)) m_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                          const double* __restrict__ x, double* __restrict__ r, int kper, int xcd,
                                                          Reduce R)
 {
     OpResidual<double> op{f, x, r};
     double acc[2] = {0.0, 0.0};
-    march<double, BX, RHO>(L, kper, xcd, op, acc);
+    march<double, BX, WM>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 

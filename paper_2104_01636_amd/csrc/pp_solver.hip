@@ -174,6 +174,7 @@ struct Level64 {  // float64 coefficients of a coarse level (set-up and float64 
 };
 struct Level32 {
     float *wx = nullptr, *wy = nullptr, *wz = nullptr, *invd = nullptr;
+    __half *hx = nullptr, *hy = nullptr, *hz = nullptr;  // float16 weights (coarse levels)
 };
 
 template <class T>
@@ -219,6 +220,7 @@ struct Params {
     int tail_max = 1024;        // largest level the one-launch cycle starts on (at most kTailMaxCells)
     double wc = 2.0;
     bool graphs = true;
+    bool hw = true;             // float16 face weights for the float32 cycle below the finest level
     int fuse = 1;               // levels smoothed once: first sweep with restriction, and
                                 // prolongation with the last half-sweep, as overlapped-tile
                                 // launches on float32 levels (1), on every level (2) or nowhere
@@ -447,6 +449,11 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
             c32[l].wy = P.take<float>(nn(l));
             c32[l].wz = P.take<float>(nn(l));
             c32[l].invd = P.take<float>(nn(l));
+            if (l >= 1 && prm.hw) {
+                c32[l].hx = P.take<__half>(nn(l));
+                c32[l].hy = P.take<__half>(nn(l));
+                c32[l].hz = P.take<__half>(nn(l));
+            }
         }
     }
     const size_t nd = nn(nl - 1);
@@ -512,6 +519,9 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         for (int l = 0; l < nl; ++l) {
             h64.L[l].v = LevelView<double>{nx[l], ny[l], nz[l], c64[l].wx, c64[l].wy, c64[l].wz, c64[l].invd};
             h32.L[l].v = LevelView<float>{nx[l], ny[l], nz[l], c32[l].wx, c32[l].wy, c32[l].wz, c32[l].invd};
+            h32.L[l].v.hwx = c32[l].hx;
+            h32.L[l].v.hwy = c32[l].hy;
+            h32.L[l].v.hwz = c32[l].hz;
         }
         if (prm.rho) {
             h64.L[0].v.rho = rho64;
@@ -631,7 +641,9 @@ static LevelView<double> fine64(const Handle* H)
 template <class T>
 static double weight_arrays(const Handle* H, const LevelView<T>& v)
 {
-    return (v.rho && H->prm.march) ? 1.0 : 3.0;
+    // in units of the view's precision: density 1, float16 weights 3 halves, stored 3
+    if (!H->prm.march) return 3.0;
+    return v.rho ? 1.0 : (v.hwx ? 1.5 : 3.0);
 }
 
 // Whether a level smoothed once runs its passes as overlapped-tile launches.
@@ -645,14 +657,20 @@ static bool fused(const Handle* H, size_t prec, size_t n)
 // the stencil's own diagonal, the per-cell kernels read 1/D.
 static double invd_arrays(const Handle* H) { return H->prm.march ? 0.0 : 1.0; }
 
-template <bool B>
-using RhoC = std::integral_constant<bool, B>;
-// Calls f(RhoC<true>{}) when the view's weights come from the density.
+template <int M>
+using WmC = std::integral_constant<int, M>;
+// Calls f(WmC<m>{}) with the source m of the view's face weights for the
+// march kernels: the density, float16 copies, or the stored arrays.
 template <class T, class F>
 static void with_rho(const LevelView<T>& v, F&& f)
 {
-    if (v.rho) f(RhoC<true>{});
-    else f(RhoC<false>{});
+    if (v.rho) f(WmC<kWRho>{});
+    else if constexpr (std::is_same_v<T, float>) {
+        if (v.hwx) f(WmC<kWHalf>{});
+        else f(WmC<kWStored>{});
+    } else {
+        f(WmC<kWStored>{});
+    }
 }
 
 // XCD-aware tile order for a march launch on a level of this size (see tile_of_block).
@@ -796,12 +814,12 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
         with_bx(g.bx, [&](auto B) {
             with_rho(v, [&](auto W) {
                 constexpr int BX = decltype(B)::value;
-                constexpr bool RHO = decltype(W)::value;
+                constexpr int WM = decltype(W)::value;
                 if (use_beta)
-                    m_dir_apply<T, BX, RHO, TZ, true, FINE><<<g.grid, g.block, 0, H->stream>>>(
+                    m_dir_apply<T, BX, WM, TZ, true, FINE><<<g.grid, g.block, 0, H->stream>>>(
                         v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, g.kper, xcd_of(H, v), R);
                 else
-                    m_dir_apply<T, BX, RHO, TZ, false, FINE><<<g.grid, g.block, 0, H->stream>>>(
+                    m_dir_apply<T, BX, WM, TZ, false, FINE><<<g.grid, g.block, 0, H->stream>>>(
                         v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, g.kper, xcd_of(H, v), R);
             });
         });
@@ -1133,7 +1151,8 @@ static void set_density(Handle* H, const double* rho)
         check_launch();
         k_level_finish<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx, H->c64[l].wy,
                                                           H->c64[l].wz, H->c64[l].invd, H->c32[l].wx, H->c32[l].wy,
-                                                          H->c32[l].wz, H->c32[l].invd, g.kper);
+                                                          H->c32[l].wz, H->c32[l].invd, H->c32[l].hx, H->c32[l].hy,
+                                                          H->c32[l].hz, g.kper);
         check_launch();
     }
     if (H->M64) {
@@ -1291,6 +1310,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NU0")) p.nu0 = std::max(1, atoi(s));
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
+    if (const char* s = getenv("PP_HW")) p.hw = atoi(s) != 0;
     if (const char* s = getenv("PP_FUSE")) p.fuse = std::max(0, std::min(2, atoi(s)));
     if (const char* s = getenv("PP_PFUSE")) p.pfuse = atoi(s) != 0;
     if (const char* s = getenv("PP_FBIG")) p.fbig = std::max(0L, atol(s));

@@ -145,15 +145,17 @@ def test_duct32_against_reference(mode):
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
 @pytest.mark.parametrize("env", [{"PP_TAILMAX": "8192"}, {"PP_TAIL": "0"}, {"PP_FUSE": "0"}, {"PP_FUSE": "2"},
-                                 {"PP_PFUSE": "0"}],
-                         ids=["tail_from_8192", "no_tail", "unfused", "fused_everywhere", "fused_pre_only"])
+                                 {"PP_PFUSE": "0"}, {"PP_HW": "0"}],
+                         ids=["tail_from_8192", "no_tail", "unfused", "fused_everywhere", "fused_pre_only",
+                              "float32_coarse_weights"])
 def test_duct32_cycle_variants(mode, env, monkeypatch):
     """The other paths, read from the environment when the handle is made: a
     one-launch tail from the 8192-cell level (its first level read from global
     memory), no tail (a launch per pass, dense product on its own), and the
     passes of a once-smoothed level (first sweep + restriction, prolongation +
     last half-sweep) as separate launches everywhere, fused in float64 as well,
-    or fused before the coarse correction only."""
+    or fused before the coarse correction only, and float32 (instead of float16)
+    face weights on the float32 cycle's coarse levels."""
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     case = W.preset("duct32")
