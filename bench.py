@@ -3,9 +3,9 @@
 A step is the whole path on resident inputs: mixture density from the gas
 fraction, right-hand side from the face velocities, face coefficients and the
 multigrid hierarchy (pp_set_density), and the solve to a relative residual of
-1e-10 from a zero initial guess (pp_solve).  The headline form is float32
-multigrid-preconditioned CG inside float64 iterative refinement; the plain
-float64 form is timed the same way for the speed-up.
+1e-10 from a zero initial guess (pp_solve).  The headline form is float64
+flexible CG preconditioned by a float32 multigrid cycle (float32-refined); the
+plain float64 form is timed the same way for the speed-up.
 
 Prints one JSON line (rank 0).  Only one GPU is supported.
 """

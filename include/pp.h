@@ -49,7 +49,8 @@ typedef enum {
 
 typedef enum {
     PP_FP64 = 0,        /* every kernel in float64 */
-    PP_FP32_REFINED = 1 /* float32 multigrid-preconditioned CG inside float64 iterative refinement */
+    PP_FP32_REFINED = 1 /* float64 flexible CG (x, r, d, q, the operator and the dots in float64)
+                           preconditioned by a float32 multigrid cycle on a float32 copy of r */
 } pp_mode;
 
 typedef struct {
@@ -57,9 +58,10 @@ typedef struct {
     double h;          /* cell edge (> 0) */
     int mode;          /* pp_mode */
     double tol;        /* relative residual ||bbar - A p||_2 / ||bbar||_2 to reach (> 0) */
-    int max_iters;     /* PCG iterations (refined mode: total inner iterations); <= 0 selects 1000 */
+    int max_iters;     /* flexible-CG iterations over all passes; <= 0 selects 1000 */
     int pre_sweeps;    /* red-black Gauss-Seidel sweeps on the finest level; <= 0 selects 1 */
-    int post_sweeps;   /* sweeps on coarse levels; <= 0 selects 2 */
+    int post_sweeps;   /* sweeps on level 1 (and, in the multigrid-solver form, on every coarse
+                          level); <= 0 selects 2 */
     int flags;         /* PP_FLAG_* bits, 0 for the default solver */
     double omega;      /* SOR factor of the red-black smoother, in [0, 2); <= 0 selects 1 (Gauss-Seidel) */
 } pp_config;
@@ -70,9 +72,10 @@ typedef struct {
 #define PP_FLAG_MG_SOLVER 1
 
 typedef struct {
-    int iters;              /* PCG iterations (refined mode: outer refinement steps) */
-    int outer_iters;        /* refinement steps (0 in float64 mode) */
-    int inner_iters_total;  /* float32 PCG iterations over all refinement steps */
+    int iters;              /* flexible-CG iterations over all passes (multigrid-solver form: cycles) */
+    int outer_iters;        /* passes started from a freshly computed float64 residual f - A x (1 when
+                               the first pass meets the tolerance; 0 when the guess already does) */
+    int inner_iters_total;  /* float32 multigrid cycles applied (refined mode; 0 in float64 mode) */
     double rel_residual;    /* ||bbar - A p|| / ||bbar|| in float64 at return (library's own operator) */
     double setup_ms;        /* last pp_set_density, device time */
     double solve_ms;        /* this pp_solve, host wall time */

@@ -24,7 +24,6 @@
 // block to finish sums all partials in a fixed order.  Results therefore do
 // not depend on scheduling (bitwise repeatable).
 #pragma once
-#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -44,12 +43,23 @@ struct LevelView {
     const T* wz;    // +z face weight (the last plane's face joins plane 0)
     const T* invd;  // 1 / D_c
     const T* rho = nullptr;  // finest level: density, from which the plane-marching kernels derive the weights
-    // float16 copies of wx, wy, wz that the plane-marching kernels read instead
+    // bfloat16 copies of wx, wy, wz that the plane-marching kernels read instead
     // (coarse levels of the float32 preconditioner), or null
-    const __half* hwx = nullptr;
-    const __half* hwy = nullptr;
-    const __half* hwz = nullptr;
+    const unsigned short* hwx = nullptr;
+    const unsigned short* hwy = nullptr;
+    const unsigned short* hwz = nullptr;
 };
+
+// bfloat16: the upper 16 bits of an IEEE binary32 value, here rounded to
+// nearest (ties to even) from the lower 16; the float32 exponent range with 8
+// significant bits.  Only finite values are converted.
+__device__ inline unsigned short to_bf16(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float from_bf16(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
 // Reduction target: per-block partials and the output slots.  A reducing
 // launch writes one partial per block; k_reduce_finish, launched after it on
@@ -481,13 +491,14 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(int nx, int ny, int nz, cons
 }
 
 // 1/D of a level plus float32 copies of its weights (when the float32 arrays
-// exist) and float16 copies (when those exist).
+// exist) and bfloat16 copies (when those exist).
 __global__ void __launch_bounds__(kBlock) k_level_finish(int nx, int ny, int nz, const double* __restrict__ wx,
                                                         const double* __restrict__ wy, const double* __restrict__ wz,
                                                         double* __restrict__ invd64, float* __restrict__ wx32,
                                                         float* __restrict__ wy32, float* __restrict__ wz32,
-                                                        float* __restrict__ invd32, __half* __restrict__ wx16,
-                                                        __half* __restrict__ wy16, __half* __restrict__ wz16, int kper)
+                                                        float* __restrict__ invd32, unsigned short* __restrict__ wx16,
+                                                        unsigned short* __restrict__ wy16, unsigned short* __restrict__ wz16,
+                                                        int kper)
 {
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
@@ -505,9 +516,9 @@ __global__ void __launch_bounds__(kBlock) k_level_finish(int nx, int ny, int nz,
             invd32[c] = (float)inv;
         }
         if (wx16) {
-            wx16[c] = __float2half((float)wx[c]);
-            wy16[c] = __float2half((float)wy[c]);
-            wz16[c] = __float2half((float)wz[c]);
+            wx16[c] = to_bf16((float)wx[c]);
+            wy16[c] = to_bf16((float)wy[c]);
+            wz16[c] = to_bf16((float)wz[c]);
         }
     }
 }

@@ -73,7 +73,7 @@ constexpr int kMarchThreads = (RHO && sizeof(T) == 8) ? 512 : kBlock;
 
 // Where a march kernel's face weights come from (its WM parameter): the level's
 // stored arrays in the kernel's precision, the density (finest level), or
-// float16 copies of the stored weights (coarse levels of the float32
+// bfloat16 copies of the stored weights (coarse levels of the float32
 // preconditioner: 6 bytes per cell instead of 12).
 enum : int { kWStored = 0, kWRho = 1, kWHalf = 2 };
 
@@ -160,11 +160,11 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
             S.wxh = L.rho[c + oi];
             S.wyh = L.rho[c + oj * sy];
         } else if constexpr (HALF) {
-            S.wx = (T)__half2float(L.hwx[c]);
-            S.wy = (T)__half2float(L.hwy[c]);
-            S.wz = (T)__half2float(L.hwz[c]);
-            S.wxh = (T)__half2float(L.hwx[c + owx]);
-            S.wyh = (T)__half2float(L.hwy[c + owy]);
+            S.wx = (T)from_bf16(L.hwx[c]);
+            S.wy = (T)from_bf16(L.hwy[c]);
+            S.wz = (T)from_bf16(L.hwz[c]);
+            S.wxh = (T)from_bf16(L.hwx[c + owx]);
+            S.wyh = (T)from_bf16(L.hwy[c + owy]);
         } else {
             S.wx = L.wx[c];
             S.wy = L.wy[c];
@@ -189,7 +189,7 @@ __device__ inline void march(const LevelView<T>& L, int kper, int xcd, Op& op, A
         rho_c = L.rho[c];
         wzb = face_beta(L.rho[c + (kb0 - ks) * sz], rho_c);
     } else if constexpr (HALF) {
-        wzb = (T)__half2float(L.hwz[c + (kb0 - ks) * sz]);
+        wzb = (T)from_bf16(L.hwz[c + (kb0 - ks) * sz]);
     } else {
         wzb = L.wz[c + (kb0 - ks) * sz];
     }

@@ -174,7 +174,7 @@ struct Level64 {  // float64 coefficients of a coarse level (set-up and float64 
 };
 struct Level32 {
     float *wx = nullptr, *wy = nullptr, *wz = nullptr, *invd = nullptr;
-    __half *hx = nullptr, *hy = nullptr, *hz = nullptr;  // float16 weights (coarse levels)
+    unsigned short *hx = nullptr, *hy = nullptr, *hz = nullptr;  // bfloat16 weights (coarse levels)
 };
 
 template <class T>
@@ -220,7 +220,9 @@ struct Params {
     int tail_max = 1024;        // largest level the one-launch cycle starts on (at most kTailMaxCells)
     double wc = 2.0;
     bool graphs = true;
-    bool hw = true;             // float16 face weights for the float32 cycle below the finest level
+    bool hw = true;             // bfloat16 face weights for the float32 cycle below the finest level,
+    long hwmin = 65536;         // on levels with more cells than this (the bandwidth-bound ones; on
+                                // small grids the 8-bit significand costs iterations)
     int fuse = 1;               // levels smoothed once: first sweep with restriction, and
                                 // prolongation with the last half-sweep, as overlapped-tile
                                 // launches on float32 levels (1), on every level (2) or nowhere
@@ -449,10 +451,10 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
             c32[l].wy = P.take<float>(nn(l));
             c32[l].wz = P.take<float>(nn(l));
             c32[l].invd = P.take<float>(nn(l));
-            if (l >= 1 && prm.hw) {
-                c32[l].hx = P.take<__half>(nn(l));
-                c32[l].hy = P.take<__half>(nn(l));
-                c32[l].hz = P.take<__half>(nn(l));
+            if (l >= 1 && prm.hw && (long)nn(l) > prm.hwmin) {
+                c32[l].hx = P.take<unsigned short>(nn(l));
+                c32[l].hy = P.take<unsigned short>(nn(l));
+                c32[l].hz = P.take<unsigned short>(nn(l));
             }
         }
     }
@@ -641,7 +643,7 @@ static LevelView<double> fine64(const Handle* H)
 template <class T>
 static double weight_arrays(const Handle* H, const LevelView<T>& v)
 {
-    // in units of the view's precision: density 1, float16 weights 3 halves, stored 3
+    // in units of the view's precision: density 1, bfloat16 weights 3 halves, stored 3
     if (!H->prm.march) return 3.0;
     return v.rho ? 1.0 : (v.hwx ? 1.5 : 3.0);
 }
@@ -660,7 +662,7 @@ static double invd_arrays(const Handle* H) { return H->prm.march ? 0.0 : 1.0; }
 template <int M>
 using WmC = std::integral_constant<int, M>;
 // Calls f(WmC<m>{}) with the source m of the view's face weights for the
-// march kernels: the density, float16 copies, or the stored arrays.
+// march kernels: the density, bfloat16 copies, or the stored arrays.
 template <class T, class F>
 static void with_rho(const LevelView<T>& v, F&& f)
 {
@@ -1311,6 +1313,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_NUC")) p.nuc = std::max(1, atoi(s));
     if (const char* s = getenv("PP_GRAPHS")) p.graphs = atoi(s) != 0;
     if (const char* s = getenv("PP_HW")) p.hw = atoi(s) != 0;
+    if (const char* s = getenv("PP_HWMIN")) p.hwmin = std::max(0L, atol(s));
     if (const char* s = getenv("PP_FUSE")) p.fuse = std::max(0, std::min(2, atoi(s)));
     if (const char* s = getenv("PP_PFUSE")) p.pfuse = atoi(s) != 0;
     if (const char* s = getenv("PP_FBIG")) p.fbig = std::max(0L, atol(s));

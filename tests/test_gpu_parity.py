@@ -154,8 +154,8 @@ def test_duct32_cycle_variants(mode, env, monkeypatch):
     memory), no tail (a launch per pass, dense product on its own), and the
     passes of a once-smoothed level (first sweep + restriction, prolongation +
     last half-sweep) as separate launches everywhere, fused in float64 as well,
-    or fused before the coarse correction only, and float32 (instead of float16)
-    face weights on the float32 cycle's coarse levels."""
+    or fused before the coarse correction only, and float32 (instead of bfloat16)
+    face weights on the float32 cycle's large coarse levels."""
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     case = W.preset("duct32")
@@ -168,6 +168,27 @@ def test_duct32_cycle_variants(mode, env, monkeypatch):
         p = cpu(p)
     rr, err = check_solution(rho_ref, b_ref, case.h, p, 1e-10, p_ref)
     say("   iters", st["iters"], st["inner_iters_total"], "res", rr, "err", err, "ms", st["solve_ms"])
+
+
+@pytest.mark.parametrize("scale", [1e-6, 1e6])
+def test_density_scale_far_from_one_refined(scale, monkeypatch):
+    """Density times s: every face coefficient is divided by s, so the pressure is
+    multiplied by s (the right-hand side is unchanged).  With the float32 cycle's
+    coarse weights in bfloat16 on every coarse level (PP_HWMIN=0; by default only
+    levels above 65536 cells), weights 1e6 times larger or smaller than usual stay
+    finite and non-zero, and the solve still matches the oracle's reference
+    pressure."""
+    monkeypatch.setenv("PP_HWMIN", "0")
+    case = W.preset("duct32")
+    say("duct32 density scale", scale)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    p_ref, *_ = cref.solve(rho_ref, b_ref, case.h, tol=1e-13)
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode="fp32_refined", tol=1e-10) as S:
+        S.set_density(rho_t * scale)
+        p, st = S.solve(b_t)
+    p = cpu(p)
+    rr, err = check_solution(rho_ref * scale, b_ref, case.h, p, 1e-10, p_ref * scale)
+    say("   iters", st["iters"], "res", rr, "err", err)
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
