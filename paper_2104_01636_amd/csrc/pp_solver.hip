@@ -209,7 +209,8 @@ struct Hier {
 
 struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 3, coarse_sweeps = 16;
-    int kit2 = 4;               // K-cycle steps on levels >= 2 (0: kit)
+    int kit2 = 4;               // K-cycle steps on the deepest K-cycle level, the one whose coarse
+                                // correction is a plain V-cycle (0: kit)
     int nuk2 = 1;               // sweeps on the K-cycle levels >= 2 (0: nuc); the extra
                                 // K-cycle step there buys more than the second sweep
     int nuv = 1;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
@@ -985,7 +986,8 @@ template <class T>
 static T* kcycle(Handle* H, Hier<T>& Hh, int l)
 {
     Lev<T>& V = Hh.L[l];
-    const int kit = (l >= 2 && H->prm.kit2 > 0) ? H->prm.kit2 : H->prm.kit;
+    const bool deepest = l + 1 >= (int)Hh.L.size() || !Hh.L[l + 1].kcyc;
+    const int kit = (deepest && H->prm.kit2 > 0) ? H->prm.kit2 : H->prm.kit;
     V.d = V.d_a;
     V.d2 = V.d_b;
     for (int it = 0; it < kit; ++it) {
