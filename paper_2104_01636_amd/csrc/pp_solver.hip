@@ -209,8 +209,9 @@ struct Hier {
 
 struct Params {
     int nu0 = 1, nuc = 2, kmax = 2, kit = 3, coarse_sweeps = 16;
-    int kit2 = 4;               // K-cycle steps on the deepest K-cycle level, the one whose coarse
-                                // correction is a plain V-cycle (0: kit)
+    int kit2 = 4;               // K-cycle steps on the deepest K-cycle level (the one whose coarse
+                                // correction is a plain V-cycle) when it has more than kbig cells
+    long kbig = 262144;         // (measured: 4 steps faster on 524288-cell levels, 3 on 221184)
     int nuk2 = 1;               // sweeps on the K-cycle levels >= 2 (0: nuc); the extra
                                 // K-cycle step there buys more than the second sweep
     int nuv = 1;                // sweeps on the V-cycle levels below the K-cycles (0: nuc)
@@ -987,7 +988,7 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l)
 {
     Lev<T>& V = Hh.L[l];
     const bool deepest = l + 1 >= (int)Hh.L.size() || !Hh.L[l + 1].kcyc;
-    const int kit = (deepest && H->prm.kit2 > 0) ? H->prm.kit2 : H->prm.kit;
+    const int kit = (deepest && (long)V.n > H->prm.kbig && H->prm.kit2 > 0) ? H->prm.kit2 : H->prm.kit;
     V.d = V.d_a;
     V.d2 = V.d_b;
     for (int it = 0; it < kit; ++it) {
@@ -1325,6 +1326,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_TAILMAX")) p.tail_max = std::max(2, std::min(kTailMaxCells, atoi(s)));
     if (const char* s = getenv("PP_OMEGA")) p.omega = atof(s);
     if (const char* s = getenv("PP_KIT2")) p.kit2 = std::max(0, atoi(s));
+    if (const char* s = getenv("PP_KBIG")) p.kbig = std::max(0L, atol(s));
     if (const char* s = getenv("PP_NUV")) p.nuv = std::max(0, atoi(s));
     if (const char* s = getenv("PP_NU1")) p.nu1 = std::max(0, atoi(s));
     if (const char* s = getenv("PP_NUK2")) p.nuk2 = std::max(0, atoi(s));
