@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=24.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the solve is not sharded across GPUs); use --gpus 1",
+        print("bench.py: the solver runs on one GPU (the solve is not sharded across GPUs); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
