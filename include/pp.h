@@ -67,8 +67,9 @@ typedef struct {
 } pp_config;
 
 /* flags: run multigrid cycles as the solver, x += M (bbar - A x), instead of
- * using them to precondition conjugate gradients -- the "multigrid accelerated
- * red black SOR" form of Section 2.1.  Float64 mode only. */
+ * using them to precondition conjugate gradients -- the paper's own form
+ * (red-black SOR relaxation accelerated by multigrid, Section 2.1).  Float64
+ * mode only. */
 #define PP_FLAG_MG_SOLVER 1
 
 typedef struct {

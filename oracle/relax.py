@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY -- see the package docstring.
 
-The paper solves its pressure equations with "a multigrid accelerated red
-black SOR relaxation scheme" (Section 2.1, after eq. ppe_surface_tension) and
+The paper solves its pressure equations by red-black SOR relaxation,
+accelerated by multigrid (Section 2.1, after eq. ppe_surface_tension), and
 gives no further detail.  The pieces below are the plain definitions of the
 relaxation and of the grid transfers, written without any blocking, fusion or
 reordering.  They define iterates of the preconditioner only; the solution of

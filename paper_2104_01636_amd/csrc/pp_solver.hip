@@ -1,8 +1,8 @@
 // pp_solver.hip -- host side of the pressure solver: hierarchy, Krylov drivers, C ABI.
 //
-// Method.  The paper solves its pressure equations with "a multigrid
-// accelerated red black SOR relaxation scheme" on the GPU (Section 2.1, after
-// eq. ppe_surface_tension) and gives no further detail.  Here the same pieces
+// Method.  The paper solves its pressure equations on the GPU by red-black SOR
+// relaxation, accelerated by multigrid (Section 2.1, after eq.
+// ppe_surface_tension), and gives no further detail.  Here the same pieces
 // -- red-black Gauss-Seidel relaxation and geometric multigrid -- precondition
 // a conjugate-gradient iteration:
 //   * finest level: flexible CG (one-term recurrence) on K p = f;

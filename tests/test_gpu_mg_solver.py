@@ -1,7 +1,7 @@
 """The paper's solver form: multigrid cycles with red-black SOR as the solver (no CG).
 
-Section 2.1 names "a multigrid accelerated red black SOR relaxation scheme";
-PP_FLAG_MG_SOLVER runs the library's V-cycle (red-black SOR smoothing with a
+Section 2.1 solves the pressure equations by red-black SOR relaxation
+accelerated by multigrid; PP_FLAG_MG_SOLVER runs the library's V-cycle (red-black SOR smoothing with a
 factor omega) as a stationary iteration x += M (bbar - A x).  The answer must be
 the same discrete solution: oracle residual and reference pressure.
 """
