@@ -31,7 +31,8 @@
 namespace pp {
 
 constexpr int kBlock = 256;          // threads per block for grid kernels
-constexpr int kMaxRedBlocks = 2048;  // upper bound on blocks of a reducing launch
+constexpr int kMaxRedBlocks = 2048;  // blocks of a reducing launch, at most (the per-plane launches)
+constexpr int kMaxPartialBlocks = 4096;  // ... and of any reducing launch (the size of the partials buffer)
 constexpr int kMaxRed = 4;           // values reduced by one launch
 
 // Operator of one level, in precision T.
@@ -65,7 +66,7 @@ __device__ inline float from_bf16(unsigned short b) { return __uint_as_float((un
 // launch writes one partial per block; k_reduce_finish, launched after it on
 // the same stream, sums them in a fixed order.
 struct Reduce {
-    double* partials;    // [kMaxRedBlocks * kMaxRed]
+    double* partials;    // [kMaxPartialBlocks * kMaxRed]
     double* out;         // scalar slots receiving the totals
     int slot[kMaxRed];   // slot index per reduced value
 };

@@ -402,8 +402,12 @@ static bool valid_cfg(const pp_config* cfg, std::string* why)
             MGeo m = mgeo(cfg->nx, cfg->ny, cfg->nz, b);
             most = std::max(most, (size_t)m.grid.x * m.grid.y * m.grid.z);
         }
-        const MGeo o = ovl_geo(cfg->nx, cfg->ny, cfg->nz, kMaxRedBlocks);  // a reducing overlapped launch
-        most = std::max(most, (size_t)o.grid.x * o.grid.y * o.grid.z);
+        // a reducing overlapped launch may use the whole partials buffer
+        const MGeo o = ovl_geo(cfg->nx, cfg->ny, cfg->nz, kMaxPartialBlocks);
+        if ((size_t)o.grid.x * o.grid.y * o.grid.z > (size_t)kMaxPartialBlocks) {
+            if (why) *why = "cross-section too large for the overlapped-tile launches";
+            return false;
+        }
         if (most > (size_t)kMaxRedBlocks) {
             if (why) *why = "cross-section too large (more than 2048 thread tiles per plane)";
             return false;
@@ -508,7 +512,7 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     // the finest cycle reads the Krylov residual
     if (fp64) h64.L[0].rhs = r64;
     else h32.L[0].rhs = r32;
-    double* partials = P.take<double>((size_t)kMaxRedBlocks * kMaxRed);
+    double* partials = P.take<double>((size_t)kMaxPartialBlocks * kMaxRed);
     double* slots = P.take<double>(kSlots);
 
     if (H && base) {
@@ -776,9 +780,9 @@ template <class T, int NDOT, class TQ>
 static dim3 launch_prolong_half(Handle* H, const LevelView<T>& v, const T* f, const T* x, const T* e, T wc, T* z,
                                 const TQ* q, const Reduce& R)
 {
-    // a reducing launch writes one partial per block: at most kMaxRedBlocks blocks
-    const MGeo g = ovl_geo(v.nx, v.ny, v.nz, NDOT > 0 ? std::min(H->prm.oblocks, kMaxRedBlocks) : H->prm.oblocks);
-    if (NDOT > 0 && (size_t)g.grid.x * g.grid.y * g.grid.z > (size_t)kMaxRedBlocks)
+    // a reducing launch writes one partial per block: at most kMaxPartialBlocks blocks
+    const MGeo g = ovl_geo(v.nx, v.ny, v.nz, NDOT > 0 ? std::min(H->prm.oblocks, kMaxPartialBlocks) : H->prm.oblocks);
+    if (NDOT > 0 && (size_t)g.grid.x * g.grid.y * g.grid.z > (size_t)kMaxPartialBlocks)
         throw Fail(PP_ERR_INVALID, "cross-section too large for a reducing overlapped-tile launch");
     const int xcd = H->prm.oxcd < 0 ? xcd_of(H, v) : H->prm.oxcd;
     with_rho(v, [&](auto W) {
