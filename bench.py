@@ -99,6 +99,70 @@ def serving_leg(args, dev, log):
     return out
 
 
+def next_rows_leg(args, case, log, alpha_t, u_t, v_t, w_t, rho_t, rhs_t, p_t):
+    """The steps on either side of the solve and the paper's own solver form, on the same input.
+
+    * Time per call of the mixture density, the divergence (step 11's right-hand side), the face
+      projection (step 12) and the surface-tension right-hand side (eq. ppe_surface_tension):
+      torch events on the current stream, which is the stream the library launches them on,
+      around repeated calls.  Each call ends by synchronising its stream, so the time per call
+      includes one launch gap; the rates are algorithmic bytes (each array element read or
+      written once) over that time, a lower bound on the kernel's own rate.
+    * Multigrid as the solver (red-black SOR V-cycles, no CG; Section 2.1) in float64, to the
+      same tolerance from a zero guess, for SOR factors 1.0 and 1.15."""
+    import torch
+    from paper_2104_01636_amd import ppsolve
+
+    n = case.n_cells
+    reps = 10
+    kappa_t = torch.full_like(alpha_t, 2.0 / (0.5 * case.diameter * case.h))  # curvature of a bubble
+    out_t = torch.empty_like(alpha_t)
+    u2, v2, w2 = u_t.clone(), v_t.clone(), w_t.clone()
+    calls = {  # name: (launch, algorithmic bytes per cell)
+        "density_from_fraction": (lambda: ppsolve.density_from_fraction(alpha_t, 1000.0, 1.2, out=out_t), 16),
+        "divergence": (lambda: ppsolve.divergence(u_t, v_t, w_t, case.h, 1.0, out=out_t), 32),
+        "project": (lambda: ppsolve.project(rho_t, p_t, u2, v2, w2, case.h, 1e-3), 64),
+        "surface_tension_rhs": (lambda: ppsolve.surface_tension_rhs(rho_t, alpha_t, kappa_t, 0.072, case.h,
+                                                                    out=out_t), 32),
+    }
+    kern = {}
+    for name, (call, bpc) in calls.items():
+        call()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = bpc * n / (us * 1e-6) / 1e9
+        kern[name] = {"us_per_call": round(us, 2), "calls": reps, "bytes_per_cell": bpc, "GB_per_s": round(gbs, 1),
+                      "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"next rows: {name} {us:.1f} us, {gbs:.0f} GB/s")
+    del u2, v2, w2, kappa_t, out_t
+
+    mg = {}
+    for omega in (1.0, 1.15):
+        with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, tol=args.tol, max_iters=4000,
+                            flags=ppsolve.PP_FLAG_MG_SOLVER, omega=omega) as S:
+            S.set_density(rho_t)
+            times = []
+            for k in range(2):  # the first solve is a warm-up
+                p_t.zero_()
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                _, st = S.solve(rhs_t, p_t)
+                torch.cuda.synchronize()
+                if k:
+                    times.append((time.perf_counter() - a) * 1e3)
+            mg[f"omega_{omega:g}"] = {"time_to_tol_ms": round(times[0], 3), "cycles": int(st["iters"]),
+                                      "ms_per_cycle": round(st["solve_ms"] / max(1, st["iters"]), 4),
+                                      "rel_residual": float(f"{st['rel_residual']:.3e}")}
+            log(f"next rows: multigrid solver omega {omega:g}: {times[0]:.1f} ms, {st['iters']} cycles, "
+                f"residual {st['rel_residual']:.2e}")
+    return {"around_the_solve": kern, "multigrid_solver_fp64": mg}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +181,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving leg (Poisson arrivals, mixed grids); 0 skips it")
     ap.add_argument("--serving-rate", type=float, default=40.0)
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the kernels around the solve and the multigrid-as-solver form")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gb", type=float, default=24.0)
     args = ap.parse_args()
@@ -229,6 +295,10 @@ def main():
     else:
         kern_tab = {}
 
+    next_rows = None
+    if not args.no_next_rows:
+        next_rows = next_rows_leg(args, case, log, alpha_t, u_t, v_t, w_t, rho_t, rhs_t, p_t)
+
     serving = None
     if args.serving_requests > 0:
         serving = serving_leg(args, dev, log)
@@ -276,6 +346,7 @@ def main():
         "cells_per_s_solved": round(n / (ms_per_step * 1e-3), 1),
         "roofline": roof,
         "kernels": kern_tab,
+        "next_rows": next_rows,
         "serving": serving,
         "cpu_baseline": cpu,
     }

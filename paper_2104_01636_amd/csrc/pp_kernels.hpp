@@ -641,7 +641,8 @@ __global__ void __launch_bounds__(kBlock) k_apply_a(LevelView<double> L, double 
 }
 
 // Projection on faces (step 12 restricted to face velocities), in place:
-// u_f -= dt * beta_f * (p_R - p_L)/h; wall faces set to zero.
+// u_f -= dt * beta_f * (p_R - p_L)/h; wall faces set to zero.  Each thread walks
+// its z range carrying rho and p of the plane above into the next plane.
 __global__ void __launch_bounds__(kBlock) k_project(int nx, int ny, int nz, double h, double dt, const double* __restrict__ rho,
                                                    const double* __restrict__ p, double* u, double* v, double* w, int kper)
 {
@@ -649,26 +650,33 @@ __global__ void __launch_bounds__(kBlock) k_project(int nx, int ny, int nz, doub
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
     const int sy = nx, sz = nx * ny;
-    for (int k = t.k0; k < t.k1; ++k) {
-        const int c = cell(nx, ny, t.i, t.j, k);
+    int c = cell(nx, ny, t.i, t.j, t.k0);
+    double rc = rho[c], pc = p[c];
+    for (int k = t.k0; k < t.k1; ++k, c += sz) {
         const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
-        const double rc = rho[c], pc = p[c];
+        const double rt = rho[ct], pt = p[ct];
         u[c] = t.i < nx - 1 ? u[c] - dt * ((2.0 / (rc + rho[c + 1])) * ((p[c + 1] - pc) / h)) : 0.0;
         v[c] = t.j < ny - 1 ? v[c] - dt * ((2.0 / (rc + rho[c + sy])) * ((p[c + sy] - pc) / h)) : 0.0;
-        w[c] = w[c] - dt * ((2.0 / (rc + rho[ct])) * ((p[ct] - pc) / h));
+        w[c] = w[c] - dt * ((2.0 / (rc + rt)) * ((pt - pc) / h));
+        rc = rt;
+        pc = pt;
     }
 }
 
 // Right-hand side of the surface-tension pressure equation: out = div(beta f)
-// with the face force f = sigma * (kappa_L + kappa_R)/2 * (a_R - a_L)/h.
-__device__ inline double st_flux(const double* rho, const double* a, const double* kap, double sigma, double h, int L, int R)
+// with the face force f = sigma * (kappa_L + kappa_R)/2 * (a_R - a_L)/h, from
+// the values at the face's lower (L) and upper (R) cell.
+__device__ inline double st_flux(double rl, double rr, double al, double ar, double kl, double kr, double sigma, double h)
 {
 #pragma clang fp contract(off)
-    const double beta = 2.0 / (rho[L] + rho[R]);
-    const double f = sigma * (0.5 * (kap[L] + kap[R])) * ((a[R] - a[L]) / h);
+    const double beta = 2.0 / (rl + rr);
+    const double f = sigma * (0.5 * (kl + kr)) * ((ar - al) / h);
     return beta * f;
 }
 
+// Each thread walks its z range: the cell's values and its top-face flux are
+// carried into the next plane as that plane's own values and bottom-face flux
+// (the same operands in the same order, so the same rounding).
 __global__ void __launch_bounds__(kBlock) k_surface_rhs(int nx, int ny, int nz, double h, double sigma,
                                                        const double* __restrict__ rho, const double* __restrict__ a,
                                                        const double* __restrict__ kap, double* __restrict__ out, int kper)
@@ -677,17 +685,26 @@ __global__ void __launch_bounds__(kBlock) k_surface_rhs(int nx, int ny, int nz, 
     Tile t = tile(nx, ny, nz, kper);
     if (!t.act) return;
     const int sy = nx, sz = nx * ny;
-    for (int k = t.k0; k < t.k1; ++k) {
-        const int c = cell(nx, ny, t.i, t.j, k);
+    int c = cell(nx, ny, t.i, t.j, t.k0);
+    double rc = rho[c], ac = a[c], kc = kap[c];
+    double fb;
+    {
+        const int cb = t.k0 > 0 ? c - sz : c + (nz - 1) * sz;
+        fb = st_flux(rho[cb], rc, a[cb], ac, kap[cb], kc, sigma, h);
+    }
+    for (int k = t.k0; k < t.k1; ++k, c += sz) {
         const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
-        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz;
-        const double fe = t.i < nx - 1 ? st_flux(rho, a, kap, sigma, h, c, c + 1) : 0.0;
-        const double fw = t.i > 0 ? st_flux(rho, a, kap, sigma, h, c - 1, c) : 0.0;
-        const double fn = t.j < ny - 1 ? st_flux(rho, a, kap, sigma, h, c, c + sy) : 0.0;
-        const double fs = t.j > 0 ? st_flux(rho, a, kap, sigma, h, c - sy, c) : 0.0;
-        const double ft = st_flux(rho, a, kap, sigma, h, c, ct);
-        const double fb = st_flux(rho, a, kap, sigma, h, cb, c);
+        const double rt = rho[ct], at = a[ct], kt = kap[ct];
+        const double fe = t.i < nx - 1 ? st_flux(rc, rho[c + 1], ac, a[c + 1], kc, kap[c + 1], sigma, h) : 0.0;
+        const double fw = t.i > 0 ? st_flux(rho[c - 1], rc, a[c - 1], ac, kap[c - 1], kc, sigma, h) : 0.0;
+        const double fn = t.j < ny - 1 ? st_flux(rc, rho[c + sy], ac, a[c + sy], kc, kap[c + sy], sigma, h) : 0.0;
+        const double fs = t.j > 0 ? st_flux(rho[c - sy], rc, a[c - sy], ac, kap[c - sy], kc, sigma, h) : 0.0;
+        const double ft = st_flux(rc, rt, ac, at, kc, kt, sigma, h);
         out[c] = (((fe - fw) + (fn - fs)) + (ft - fb)) / h;
+        fb = ft;
+        rc = rt;
+        ac = at;
+        kc = kt;
     }
 }
 
