@@ -83,11 +83,12 @@ def test_static_bubble_surface_tension_balance(mode):
     assert cref.relative_residual(rho, rhs_ref, p, h) <= 1e-11
 
 
-@pytest.mark.parametrize("shape", [(101, 256, 256), (7, 33, 5)])
+@pytest.mark.parametrize("shape", [(101, 256, 256), (7, 33, 5), (512, 256, 256)])
 def test_projection_and_surface_rhs_bitexact_multi_plane(shape):
     """The two kernels walk a z range per thread and carry the plane above into
     the next plane.  At 256 x 256 x 101 a thread walks 4 planes and the last z
-    range holds 1; 5 x 33 x 7 is a ragged cross-section.  Random fields, so no
+    range holds 1; 5 x 33 x 7 is a ragged cross-section; 256 x 256 x 512 is the
+    benchmark's size and launch (16 planes per thread).  Random fields, so no
     face value is special; both must match the oracle bit for bit."""
     nz, ny, nx = shape
     print("multi-plane", shape, flush=True)
