@@ -676,31 +676,44 @@ __device__ inline double st_flux(double rl, double rr, double al, double ar, dou
 
 // Each thread walks its z range: the cell's values and its top-face flux are
 // carried into the next plane as that plane's own values and bottom-face flux
-// (the same operands in the same order, so the same rounding).
+// (the same operands in the same order, so the same rounding).  In a plane each
+// thread forms its east and north faces; the west face is the east face of the
+// lane before it (same row of the tile) and the south face the north face of
+// the row below it (through LDS), so a face shared by two cells of the tile is
+// formed once.  Threads outside the grid read clamped cells, take part in the
+// exchanges and barriers, and store nothing.
 __global__ void __launch_bounds__(kBlock) k_surface_rhs(int nx, int ny, int nz, double h, double sigma,
                                                        const double* __restrict__ rho, const double* __restrict__ a,
                                                        const double* __restrict__ kap, double* __restrict__ out, int kper)
 {
 #pragma clang fp contract(off)
-    Tile t = tile(nx, ny, nz, kper);
-    if (!t.act) return;
+    __shared__ double sfn[2][kBlock];  // north-face flux of each thread's cell, by plane parity
+    const Tile t = tile(nx, ny, nz, kper);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int sy = nx, sz = nx * ny;
-    int c = cell(nx, ny, t.i, t.j, t.k0);
+    const int ic = min(t.i, nx - 1), jc = min(t.j, ny - 1);
+    int c = cell(nx, ny, ic, jc, t.k0);
     double rc = rho[c], ac = a[c], kc = kap[c];
     double fb;
     {
         const int cb = t.k0 > 0 ? c - sz : c + (nz - 1) * sz;
         fb = st_flux(rho[cb], rc, a[cb], ac, kap[cb], kc, sigma, h);
     }
-    for (int k = t.k0; k < t.k1; ++k, c += sz) {
+    int par = 0;
+    for (int k = t.k0; k < t.k1; ++k, c += sz, par ^= 1) {
         const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
         const double rt = rho[ct], at = a[ct], kt = kap[ct];
-        const double fe = t.i < nx - 1 ? st_flux(rc, rho[c + 1], ac, a[c + 1], kc, kap[c + 1], sigma, h) : 0.0;
-        const double fw = t.i > 0 ? st_flux(rho[c - 1], rc, a[c - 1], ac, kap[c - 1], kc, sigma, h) : 0.0;
-        const double fn = t.j < ny - 1 ? st_flux(rc, rho[c + sy], ac, a[c + sy], kc, kap[c + sy], sigma, h) : 0.0;
-        const double fs = t.j > 0 ? st_flux(rho[c - sy], rc, a[c - sy], ac, kap[c - sy], kc, sigma, h) : 0.0;
+        const double fe = ic < nx - 1 ? st_flux(rc, rho[c + 1], ac, a[c + 1], kc, kap[c + 1], sigma, h) : 0.0;
+        const double fn = jc < ny - 1 ? st_flux(rc, rho[c + sy], ac, a[c + sy], kc, kap[c + sy], sigma, h) : 0.0;
+        double fw = __shfl_up(fe, 1, 64);
+        if (threadIdx.x == 0) fw = ic > 0 ? st_flux(rho[c - 1], rc, a[c - 1], ac, kap[c - 1], kc, sigma, h) : 0.0;
+        sfn[par][tid] = fn;
+        __syncthreads();
+        double fs;
+        if (threadIdx.y > 0) fs = sfn[par][tid - blockDim.x];
+        else fs = jc > 0 ? st_flux(rho[c - sy], rc, a[c - sy], ac, kap[c - sy], kc, sigma, h) : 0.0;
         const double ft = st_flux(rc, rt, ac, at, kc, kt, sigma, h);
-        out[c] = (((fe - fw) + (fn - fs)) + (ft - fb)) / h;
+        if (t.act) out[c] = (((fe - fw) + (fn - fs)) + (ft - fb)) / h;
         fb = ft;
         rc = rt;
         ac = at;
