@@ -605,22 +605,36 @@ __global__ void __launch_bounds__(kBlock) k_density(size_t n, const double* __re
 }
 
 // out = (((u_e - u_w) + (v_n - v_s)) + (w_t - w_b)) / (h*dt); wall faces carry zero.
+// Each thread walks its z range carrying w of the plane below; u of the west
+// cell comes from the lane before it, v of the south cell from the row below
+// (LDS, one barrier per plane).  Threads outside the grid read clamped cells,
+// take part in the exchanges and barriers, and store nothing.
 __global__ void __launch_bounds__(kBlock) k_divergence(int nx, int ny, int nz, double hd, const double* __restrict__ u,
                                                       const double* __restrict__ v, const double* __restrict__ w,
                                                       double* __restrict__ out, int kper)
 {
 #pragma clang fp contract(off)
-    Tile t = tile(nx, ny, nz, kper);
-    if (!t.act) return;
+    __shared__ double sv[2][kBlock];  // v of each thread's cell, by plane parity
+    const Tile t = tile(nx, ny, nz, kper);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int sy = nx, sz = nx * ny;
-    for (int k = t.k0; k < t.k1; ++k) {
-        const int c = cell(nx, ny, t.i, t.j, k);
-        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz;
-        const double ue = t.i < nx - 1 ? u[c] : 0.0;
-        const double uw = t.i > 0 ? u[c - 1] : 0.0;
-        const double vn = t.j < ny - 1 ? v[c] : 0.0;
-        const double vs = t.j > 0 ? v[c - sy] : 0.0;
-        out[c] = (((ue - uw) + (vn - vs)) + (w[c] - w[cb])) / hd;
+    const int ic = min(t.i, nx - 1), jc = min(t.j, ny - 1);
+    int c = cell(nx, ny, ic, jc, t.k0);
+    double wb = w[t.k0 > 0 ? c - sz : c + (nz - 1) * sz];
+    int par = 0;
+    for (int k = t.k0; k < t.k1; ++k, c += sz, par ^= 1) {
+        const double uc = u[c], vc = v[c], wc = w[c];
+        double uw = __shfl_up(uc, 1, 64);
+        if (threadIdx.x == 0) uw = ic > 0 ? u[c - 1] : 0.0;
+        sv[par][tid] = vc;
+        __syncthreads();
+        double vs;
+        if (threadIdx.y > 0) vs = sv[par][tid - blockDim.x];
+        else vs = jc > 0 ? v[c - sy] : 0.0;
+        const double ue = ic < nx - 1 ? uc : 0.0;
+        const double vn = jc < ny - 1 ? vc : 0.0;
+        if (t.act) out[c] = (((ue - uw) + (vn - vs)) + (wc - wb)) / hd;
+        wb = wc;
     }
 }
 
@@ -642,22 +656,46 @@ __global__ void __launch_bounds__(kBlock) k_apply_a(LevelView<double> L, double 
 
 // Projection on faces (step 12 restricted to face velocities), in place:
 // u_f -= dt * beta_f * (p_R - p_L)/h; wall faces set to zero.  Each thread walks
-// its z range carrying rho and p of the plane above into the next plane.
+// its z range carrying rho and p of the plane above into the next plane; rho
+// and p of the east cell come from the lane after it, of the north cell from
+// the row above (LDS, one barrier per plane).  Threads outside the grid read
+// clamped cells, take part in the exchanges and barriers, and store nothing.
 __global__ void __launch_bounds__(kBlock) k_project(int nx, int ny, int nz, double h, double dt, const double* __restrict__ rho,
                                                    const double* __restrict__ p, double* u, double* v, double* w, int kper)
 {
 #pragma clang fp contract(off)
-    Tile t = tile(nx, ny, nz, kper);
-    if (!t.act) return;
+    __shared__ double sr[2][kBlock], sp[2][kBlock];  // rho and p of each thread's cell, by plane parity
+    const Tile t = tile(nx, ny, nz, kper);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int sy = nx, sz = nx * ny;
-    int c = cell(nx, ny, t.i, t.j, t.k0);
+    const int ic = min(t.i, nx - 1), jc = min(t.j, ny - 1);
+    int c = cell(nx, ny, ic, jc, t.k0);
     double rc = rho[c], pc = p[c];
-    for (int k = t.k0; k < t.k1; ++k, c += sz) {
+    int par = 0;
+    for (int k = t.k0; k < t.k1; ++k, c += sz, par ^= 1) {
         const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
         const double rt = rho[ct], pt = p[ct];
-        u[c] = t.i < nx - 1 ? u[c] - dt * ((2.0 / (rc + rho[c + 1])) * ((p[c + 1] - pc) / h)) : 0.0;
-        v[c] = t.j < ny - 1 ? v[c] - dt * ((2.0 / (rc + rho[c + sy])) * ((p[c + sy] - pc) / h)) : 0.0;
-        w[c] = w[c] - dt * ((2.0 / (rc + rt)) * ((pt - pc) / h));
+        double re = __shfl_down(rc, 1, 64), pe = __shfl_down(pc, 1, 64);
+        if (threadIdx.x == blockDim.x - 1 && ic < nx - 1) {
+            re = rho[c + 1];
+            pe = p[c + 1];
+        }
+        sr[par][tid] = rc;
+        sp[par][tid] = pc;
+        __syncthreads();
+        double rn = rc, pn = pc;
+        if (threadIdx.y < blockDim.y - 1) {
+            rn = sr[par][tid + blockDim.x];
+            pn = sp[par][tid + blockDim.x];
+        } else if (jc < ny - 1) {
+            rn = rho[c + sy];
+            pn = p[c + sy];
+        }
+        if (t.act) {
+            u[c] = ic < nx - 1 ? u[c] - dt * ((2.0 / (rc + re)) * ((pe - pc) / h)) : 0.0;
+            v[c] = jc < ny - 1 ? v[c] - dt * ((2.0 / (rc + rn)) * ((pn - pc) / h)) : 0.0;
+            w[c] = w[c] - dt * ((2.0 / (rc + rt)) * ((pt - pc) / h));
+        }
         rc = rt;
         pc = pt;
     }

@@ -85,11 +85,12 @@ def test_static_bubble_surface_tension_balance(mode):
 
 @pytest.mark.parametrize("shape", [(101, 256, 256), (7, 33, 5), (512, 256, 256)])
 def test_projection_and_surface_rhs_bitexact_multi_plane(shape):
-    """The two kernels walk a z range per thread and carry the plane above into
-    the next plane.  At 256 x 256 x 101 a thread walks 4 planes and the last z
+    """The divergence, projection and surface-tension kernels walk a z range per
+    thread, carry values from plane to plane and share neighbour values between
+    lanes and rows of a tile.  At 256 x 256 x 101 a thread walks 4 planes and the last z
     range holds 1; 5 x 33 x 7 is a ragged cross-section; 256 x 256 x 512 is the
     benchmark's size and launch (16 planes per thread).  Random fields, so no
-    face value is special; both must match the oracle bit for bit."""
+    face value is special; all three must match the oracle bit for bit."""
     nz, ny, nx = shape
     print("multi-plane", shape, flush=True)
     rng = np.random.default_rng(11)
@@ -101,6 +102,7 @@ def test_projection_and_surface_rhs_bitexact_multi_plane(shape):
     u, v, w = (rng.normal(size=shape) for _ in range(3))
     rhs_ref = P.surface_tension_rhs(rho, a, kap, 0.072, h)
     np.testing.assert_array_equal(c(ppsolve.surface_tension_rhs(g(rho), g(a), g(kap), 0.072, h)), rhs_ref)
+    np.testing.assert_array_equal(c(ppsolve.divergence(g(u), g(v), g(w), h, 0.5)), P.divergence(u, v, w, h, 0.5))
     un, vn, wn = P.project(rho, p, u, v, w, h, 0.25)
     u_t, v_t, w_t = g(u), g(v), g(w)
     ppsolve.project(g(rho), g(p), u_t, v_t, w_t, h, 0.25)
