@@ -126,6 +126,43 @@ def test_operator_matches_sparse_incidence_construction(shape):
     np.testing.assert_allclose(cref.apply_operator(rho, p, h), ref, rtol=0, atol=1e-13 * scale)
 
 
+@pytest.mark.parametrize("shape", [(4, 3, 5), (6, 4, 4), (2, 5, 3)])
+def test_relative_residual_two_sided_against_sparse_operator(shape):
+    """The acceptance number ||bbar - A p|| / ||bbar|| (bbar = b - mean b) of both
+    oracle implementations equals the one formed from the sparse incidence operator,
+    on iterates far from converged (so a ratio that is squared, not mean-shifted, or
+    normalised by ||b|| instead of ||bbar||, differs by far more than the tolerance)."""
+    h = 1.0 / shape[2]
+    rho = rand_rho(shape, 40 + sum(shape))
+    rng = np.random.default_rng(41)
+    b = rng.standard_normal(shape) + 3.0          # mean far from zero: bbar != b
+    A = sparse_operator(rho, h)
+    bb = b.ravel() - b.mean()
+    p_exact = P.solve_dense(rho, b, h)
+    for mix in (0.0, 0.5, 0.9, 1.0 - 1e-6):
+        p = mix * p_exact + (1.0 - mix) * rng.standard_normal(shape) * np.abs(p_exact).max()
+        expect = np.linalg.norm(bb - A @ p.ravel()) / np.linalg.norm(bb)
+        assert 1e-7 < expect
+        got_py = P.relative_residual(rho, b, p, h)
+        got_c = cref.relative_residual(rho, b, p, h)
+        assert got_py == pytest.approx(expect, rel=1e-12)
+        assert got_c == pytest.approx(expect, rel=1e-12)
+    # the exact solution: residual at the rounding level, and a constant shift changes nothing
+    assert P.relative_residual(rho, b, p_exact + 11.0, h) < 1e-12
+    assert cref.relative_residual(rho, b, p_exact + 11.0, h) < 1e-12
+
+
+def test_relative_linf_error_worked_values():
+    """||(p - mean p) - (q - mean q)||_inf / ||q - mean q||_inf on hand-computed cases."""
+    q = np.array([1.0, -1.0, 2.0, -2.0])                       # zero mean, max |q| = 2
+    assert P.relative_linf_error(q + np.array([0.1, 0.0, 0.0, -0.1]) + 7.0, q) == pytest.approx(0.05, rel=1e-14)
+    # a perturbation with mean 0.1: after removing it the difference is (0.3, -0.1, -0.1, -0.1)
+    assert P.relative_linf_error(q + np.array([0.4, 0.0, 0.0, 0.0]), q) == pytest.approx(0.15, rel=1e-14)
+    # the reference's own mean is removed before its norm is taken: q + 5 has the same error
+    assert P.relative_linf_error(q + np.array([0.4, 0.0, 0.0, 0.0]), q + 5.0) == pytest.approx(0.15, rel=1e-14)
+    assert P.relative_linf_error(-q, q) == pytest.approx(2.0, rel=1e-15)
+
+
 def test_operator_invariants_and_null_space():
     shape = (8, 4, 4)
     h = 0.25
