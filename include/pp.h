@@ -104,8 +104,35 @@ int pp_set_density(pp_handle h, const double* rho);
 int pp_solve(pp_handle h, const double* rhs, double* p, pp_stats* st);
 
 /* y = A x (device, N values each) with the density of the last
- * pp_set_density: the discrete div(beta grad x) of step 11. */
+ * pp_set_density: the discrete div(beta grad x) of step 11, computed by the
+ * same plane-marching kernel, tiles and float64 face coefficients (formed from
+ * the density) as the solve's own operator passes. */
 int pp_apply(pp_handle h, const double* x, double* y);
+
+/* The two legs of the multigrid cycle on the finest level (red-black SOR
+ * relaxation accelerated by multigrid, Section 2.1), run by exactly the
+ * kernels the preconditioner uses there, on caller arrays.  They work on the
+ * scaled equation K x = f with K = -h^2 A (positive semi-definite: (K x)_c =
+ * D_c x_c - sum_f beta_f x_nb(f), D_c = sum_f beta_f).  Arrays are in the
+ * preconditioner's precision: float64 for a PP_FP64 handle, float32 for
+ * PP_FP32_REFINED.  f, x, z hold N values; rc and e hold the N/8 values of the
+ * first coarse level (nx/2 x ny/2 x nz/2, same layout).  The grid must coarsen
+ * (nx, ny even, nz divisible by 4, N > 64), else PP_ERR_INVALID; before
+ * pp_set_density, PP_ERR_STATE.  Both return after the work is done.
+ *
+ * pp_presmooth_restrict: x = the pre-smoothing from a zero guess (pre_sweeps
+ * red-black sweeps, red first), rc = the residual f - K x summed over the 8
+ * children of each coarse cell. */
+int pp_presmooth_restrict(pp_handle h, const void* f, void* x, void* rc);
+
+/* pp_prolong_postsmooth: z = x + wc * (P e) with P the injection (each fine
+ * cell takes its parent's value), followed by pre_sweeps red-black sweeps of
+ * K z = f, black first.  With q (float64 device array of N values, may be
+ * NULL) also dots[0] = sum(z) and dots[1] = <z, q> (host array of 2, float64
+ * accumulation in a fixed order), the two reductions the Krylov step takes from
+ * this pass. */
+int pp_prolong_postsmooth(pp_handle h, const void* f, const void* x, const void* e, double wc, void* z, const double* q,
+                          double* dots);
 
 /* Release everything the handle holds.  NULL is accepted. */
 int pp_destroy(pp_handle h);
@@ -147,6 +174,21 @@ int pp_project(int nx, int ny, int nz, double h, double dt, const double* rho, c
  * values; wall faces carry no force. */
 int pp_surface_tension_rhs(int nx, int ny, int nz, double h, double sigma, const double* rho, const double* alpha,
                            const double* kappa, double* out, void* hip_stream);
+
+/* Relative residual of a pressure field on the device:
+ *     *rel_out = ||bbar - A p||_2 / ||bbar||_2,   bbar = rhs - mean(rhs),
+ * with A the operator of step 11 (face coefficients 2/(rho_L + rho_R), walls
+ * in x and y, periodic in z) -- the acceptance measure of a solve, taken on the
+ * GPU from the density alone, float64 throughout, sums in a fixed order (bitwise
+ * repeatable).  0 when bbar and the residual are both zero, +inf when only bbar
+ * is.  rho, rhs, p: device arrays of N values; rel_out: host double.  The
+ * call allocates (and frees) a small device buffer for its partial sums, and
+ * returns after the work on hip_stream (may be NULL) is done.  Errors:
+ * PP_ERR_INVALID (sizes, h <= 0, null pointers, more than 4096 tiles of 64 x 8
+ * cells per plane), PP_ERR_NONFINITE (rho not finite or not > 0, rhs not
+ * finite), PP_ERR_OOM. */
+int pp_rel_residual(int nx, int ny, int nz, double h, const double* rho, const double* rhs, const double* p, double* rel_out,
+                    void* hip_stream);
 
 /* Device time of the finest-level kernels, measured with HIP events on the
  * handle's stream around each launch.

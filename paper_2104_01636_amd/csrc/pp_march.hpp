@@ -402,6 +402,45 @@ struct OpResidual {  // r = f - K x; dots ||r||^2, sum r
     }
 };
 
+template <class T>
+struct OpApply {  // y = A x = -(K x) / h^2, the operator of step 11 on its own
+    const T* x;
+    T* y;
+    T inv_h2;
+    using Raw = T;
+    using Ex = None;
+    __device__ Raw load(int c, int, int, int) const { return x[c]; }
+    __device__ T val(Raw a) const { return a; }
+    __device__ Ex extra(int) const { return {}; }
+    template <class A>
+    __device__ void apply(int c, int, int, int, T vc, Raw, const Ex&, const Stencil<T>& st, A&, bool act) const
+    {
+        if (act) y[c] = (st.s - st.d * vc) * inv_h2;
+    }
+};
+
+// ||bbar - A p||^2 and ||bbar||^2 with bbar = b - mean(b), the mean read from
+// a slot: the relative residual of step 11 measured on the device.
+struct OpRelResidual {
+    const double* p;
+    const double* b;
+    double inv_h2, mean;
+    using Raw = double;
+    using Ex = double;
+    __device__ Raw load(int c, int, int, int) const { return p[c]; }
+    __device__ double val(Raw a) const { return a; }
+    __device__ Ex extra(int c) const { return b[c]; }
+    template <class A>
+    __device__ void apply(int, int, int, int, double vc, Raw, Ex bc, const Stencil<double>& st, A& acc, bool act) const
+    {
+        if (!act) return;
+        const double bb = bc - mean;
+        const double r = bb - (st.s - st.d * vc) * inv_h2;
+        acc[0] += r * r;
+        acc[1] += bb * bb;
+    }
+};
+
 // Residual f - K x summed over the 8 children of each coarse cell.  The 2 x 2
 // children of a plane sit on lanes (l, l+1) of rows (ty, ty+1), which share a
 // wavefront for BX <= 32; the two planes of a pair are consecutive steps of the
@@ -648,6 +687,30 @@ __global__ void __launch_bounds__((kMarchThreads<T, WM == kWRho>)) m_dir_apply(L
                                 (FINE && BETA) ? (T)aprev.get() : T(0)};
     double acc[2] = {0.0, 0.0};
     march<T, BX, WM>(L, kper, xcd, op, acc);
+    reduce_finish<2>(acc, R);
+}
+
+// y = A x on the finest level with the march kernels' weights (the same tiles,
+// neighbour exchange and density-formed face coefficients as the solve's passes).
+template <int BX, int WM>
+__global__ void __launch_bounds__((kMarchThreads<double, WM == kWRho>)) m_apply(LevelView<double> L, const double* __restrict__ x,
+                                                                             double* __restrict__ y, double inv_h2,
+                                                                             int kper, int xcd)
+{
+    OpApply<double> op{x, y, inv_h2};
+    double acc[1] = {0.0};
+    march<double, BX, WM>(L, kper, xcd, op, acc);
+}
+
+// Sums of OpRelResidual over the grid (weights formed from the density).
+template <int BX>
+__global__ void __launch_bounds__((kMarchThreads<double, true>)) m_rel_residual(LevelView<double> L, const double* __restrict__ p,
+                                                                              const double* __restrict__ b, double inv_h2,
+                                                                              Coefs mean, int kper, Reduce R)
+{
+    OpRelResidual op{p, b, inv_h2, mean.get()};
+    double acc[2] = {0.0, 0.0};
+    march<double, BX, kWRho>(L, kper, 0, op, acc);
     reduce_finish<2>(acc, R);
 }
 

@@ -166,9 +166,12 @@ struct pp_server_s {
     std::vector<std::thread> workers;
     std::string err = "no error";
 
-    // Returns the index of the first admissible request, evicting idle cases as
-    // needed; -1 when none can start now.  Called with m held.
-    int pick()
+    // Returns the index of the first admissible request, or -1 when none can
+    // start now.  When the request needs idle resident cases evicted to fit,
+    // they are detached here (taken out of the case map, so nothing else picks
+    // them) and moved to *evict; their bytes stay counted in `resident` until the
+    // worker has closed them outside the lock.  Called with m held.
+    int pick(std::vector<std::unique_ptr<Case>>* evict)
     {
         for (size_t qi = 0; qi < queue.size(); ++qi) {
             Request& r = *queue[qi];
@@ -185,7 +188,8 @@ struct pp_server_s {
             for (auto& kv : cases)
                 if (!kv.second->busy && !kv.second->opening) idle += kv.second->bytes;
             if (resident - idle + need > cfg.budget_bytes) continue;  // must wait for running cases
-            while (resident + need > cfg.budget_bytes) {
+            size_t freed = 0;
+            while (resident - freed + need > cfg.budget_bytes) {
                 Case* lru = nullptr;
                 for (auto& kv : cases) {
                     Case* c = kv.second.get();
@@ -193,14 +197,31 @@ struct pp_server_s {
                     if (!lru || c->last_use < lru->last_use) lru = c;
                 }
                 if (!lru) break;
-                be.close_case(be.ctx, lru->state);
-                resident -= lru->bytes;
+                freed += lru->bytes;
                 ++evictions;
-                cases.erase(lru->id);
+                auto node = cases.find(lru->id);
+                evict->push_back(std::move(node->second));
+                cases.erase(node);
             }
             return (int)qi;
         }
         return -1;
+    }
+
+    // Closes evicted cases (m not held), then returns their bytes to the budget.
+    void close_evicted(std::unique_lock<std::mutex>& lk, std::vector<std::unique_ptr<Case>>& evict)
+    {
+        if (evict.empty()) return;
+        lk.unlock();
+        size_t freed = 0;
+        for (auto& c : evict) {
+            if (c->state) be.close_case(be.ctx, c->state);
+            freed += c->bytes;
+        }
+        evict.clear();
+        lk.lock();
+        resident -= freed;
+        cv_work.notify_all();
     }
 
     void finish(std::shared_ptr<Request> r, int status)
@@ -215,10 +236,14 @@ struct pp_server_s {
     void worker()
     {
         std::unique_lock<std::mutex> lk(m);
+        std::vector<std::unique_ptr<Case>> evict;
         for (;;) {
             int qi = -1;
-            cv_work.wait(lk, [&] { return stop || (!queue.empty() && (qi = pick()) >= 0); });
-            if (stop) return;
+            cv_work.wait(lk, [&] { return stop || (!queue.empty() && (qi = pick(&evict)) >= 0); });
+            if (stop) {
+                close_evicted(lk, evict);
+                return;
+            }
             std::shared_ptr<Request> r = queue[qi];
             queue.erase(queue.begin() + qi);
             r->t_start = now_s();
@@ -241,9 +266,15 @@ struct pp_server_s {
                 nc->opening = true;
                 c = nc.get();
                 cases[r->case_id] = std::move(nc);
+                // the new case's bytes are counted before the evicted ones are returned, so
+                // no other slot can admit into memory that is not free yet
                 resident += need;
-                peak_resident = std::max(peak_resident, resident);
                 fresh = true;
+                c->busy = true;
+                ++running;
+                max_running = std::max(max_running, running);
+                close_evicted(lk, evict);
+                peak_resident = std::max(peak_resident, resident);
             } else {
                 c = it->second.get();
                 if (!same_grid(c->cfg, r->cfg)) {
@@ -254,9 +285,11 @@ struct pp_server_s {
                     continue;
                 }
             }
-            c->busy = true;
-            ++running;
-            max_running = std::max(max_running, running);
+            if (!fresh) {
+                c->busy = true;
+                ++running;
+                max_running = std::max(max_running, running);
+            }
             lk.unlock();
 
             int rc = PP_OK;

@@ -36,6 +36,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -394,7 +395,12 @@ static bool valid_cfg(const pp_config* cfg, std::string* why)
     if (cfg->omega < 0.0 || cfg->omega >= 2.0 || !std::isfinite(cfg->omega)) { if (why) *why = "omega must be in [0, 2)"; return false; }
     if ((cfg->flags & PP_FLAG_MG_SOLVER) && cfg->mode != PP_FP64) { if (why) *why = "the multigrid-solver form is float64 only"; return false; }
     if (cfg->flags & ~PP_FLAG_MG_SOLVER) { if (why) *why = "unknown flag bits"; return false; }
-    if ((size_t)cfg->nx * cfg->ny * cfg->nz > (size_t)1 << 31) { if (why) *why = "grid too large"; return false; }
+    // 32-bit cell indices: the largest index plus one plane stride (a z-neighbour
+    // read) must fit in an int
+    if ((size_t)cfg->nx * cfg->ny * cfg->nz + (size_t)cfg->nx * cfg->ny > (size_t)INT_MAX) {
+        if (why) *why = "grid too large (32-bit cell indices)";
+        return false;
+    }
     {
         Geo g = geo(cfg->nx, cfg->ny, cfg->nz);
         size_t most = (size_t)g.grid.x * g.grid.y * g.grid.z;
@@ -862,6 +868,84 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
 template <class T>
 static T* kcycle(Handle* H, Hier<T>& Hh, int l);
 
+// Red-black sweeps of level l before and after its coarse correction.
+template <class T>
+static int sweeps_of(const Handle* H, const Lev<T>& V, int l)
+{
+    return l == 0                                             ? H->prm.nu0
+           : (l == 1 && H->prm.nu1 > 0)                       ? H->prm.nu1
+           : (V.kcyc && l >= 2 && H->prm.nuk2 > 0)            ? H->prm.nuk2
+           : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0)   ? H->prm.nuv
+                                                              : H->prm.nuc;
+}
+
+// Down leg of a cycle at level l: nu red-black sweeps of K x = f from a zero
+// guess into x, then the residual f - K x summed over the 8 children of each
+// coarse cell into rc (one overlapped-tile launch on a fused level).
+template <class T>
+static void cycle_pre(Handle* H, Lev<T>& V, int l, int nu, const T* f, T* x, T* rc)
+{
+    const bool fine = (l == 0);
+    if (nu == 1 && fused(H, sizeof(T), V.n)) {
+        // reads f, 1/D and the weights (or the density); writes x and the coarse right-hand side
+        TimeScope ts(H, fine ? kid<T>(KT_FIRST_RESTRICT) : -1, (double)V.n * sizeof(T) * (3.125 + weight_arrays(H, V.v)));
+        launch_first_restrict<T>(H, V.v, f, x, rc);
+        return;
+    }
+    {
+        // reads f, 1/D and the weights (or the density); writes x
+        TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
+        launch_first<T>(H, V.v, f, x);
+    }
+    for (int s = 1; s < nu; ++s) {
+        smooth_half(H, V, fine, f, x, 0, 0, (const T*)nullptr, l);
+        smooth_half(H, V, fine, f, x, 1, 0, (const T*)nullptr, l);
+    }
+    // reads x, f and the weights (or the density); writes the coarse right-hand side
+    TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (2.125 + weight_arrays(H, V.v)));
+    launch_restrict<T>(H, V.v, f, x, rc);
+}
+
+// Up leg of a cycle at level l: y = x + wc P e (injection), then nu sweeps
+// (black, then red) of K y = f, the first black half-sweep fused with the
+// prolongation (and, on a fused level, the red one too).  ndot: 0 none,
+// 1 sum(y), 2 sum(y) and <y, q>, reduced on the last half-sweep into level l's
+// slots.  Returns y.
+template <class T, class TQ>
+static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x, const T* e, T wc, T* y, int ndot,
+                     const TQ* q)
+{
+    const bool fine = (l == 0);
+    if (nu == 1 && H->prm.pfuse && fused(H, sizeof(T), V.n)) {
+        // reads x, f, the weights (or the density), the coarse correction and q for the dot;
+        // writes z
+        const Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
+        dim3 grid;
+        {
+            TimeScope ts(H, fine ? kid<T>(KT_PROLONG_HALF) : -1,
+                         (double)V.n * ((3.125 + weight_arrays(H, V.v)) * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
+            if (ndot == 0) grid = launch_prolong_half<T, 0, TQ>(H, V.v, f, x, e, wc, y, q, R);
+            else if (ndot == 1) grid = launch_prolong_half<T, 1, TQ>(H, V.v, f, x, e, wc, y, q, R);
+            else grid = launch_prolong_half<T, 2, TQ>(H, V.v, f, x, e, wc, y, q, R);
+        }
+        if (ndot > 0) finish(H, R, grid, ndot);
+        return y;
+    }
+    {
+        // reads x, f, the weights (or the density) and the coarse correction (the per-cell
+        // kernels also 1/D); writes y
+        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1,
+                     (double)V.n * sizeof(T) * (3.125 + invd_arrays(H) + weight_arrays(H, V.v)));
+        launch_prolong_black<T>(H, V.v, f, x, e, wc, y);
+    }
+    for (int s = 0; s < nu; ++s) {
+        if (s > 0) smooth_half(H, V, fine, f, y, 1, 0, (const T*)nullptr, l);
+        smooth_half(H, V, fine, f, y, 0, (s == nu - 1) ? ndot : 0, q, l);
+    }
+    return y;
+}
+
+
 // One multigrid cycle at level l for right-hand side f; returns the buffer holding
 // the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, reduced on the last
 // half-sweep into level l's slots.
@@ -900,30 +984,9 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         }
         return V.c;
     }
-    const int nu = fine ? H->prm.nu0
-               : (l == 1 && H->prm.nu1 > 0)                            ? H->prm.nu1
-               : (V.kcyc && l >= 2 && H->prm.nuk2 > 0)                 ? H->prm.nuk2
-               : (!V.kcyc && l > H->prm.kmax && H->prm.nuv > 0)        ? H->prm.nuv
-                                                                       : H->prm.nuc;
+    const int nu = sweeps_of(H, V, l);
     Lev<T>& C = Hh.L[l + 1];
-    if (nu == 1 && fused(H, sizeof(T), V.n)) {
-        // reads f, 1/D and the weights (or the density); writes x and the coarse right-hand side
-        TimeScope ts(H, fine ? kid<T>(KT_FIRST_RESTRICT) : -1, (double)V.n * sizeof(T) * (3.125 + weight_arrays(H, V.v)));
-        launch_first_restrict<T>(H, V.v, f, V.c, C.rhs);
-    } else {
-        {
-            // reads f, 1/D and the weights (or the density); writes x
-            TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
-            launch_first<T>(H, V.v, f, V.c);
-        }
-        for (int s = 1; s < nu; ++s) {
-            smooth_half(H, V, fine, f, V.c, 0, 0, (const T*)nullptr, l);
-            smooth_half(H, V, fine, f, V.c, 1, 0, (const T*)nullptr, l);
-        }
-        // reads x, f and the weights (or the density); writes the coarse right-hand side
-        TimeScope ts(H, fine ? kid<T>(KT_RESTRICT) : -1, (double)V.n * sizeof(T) * (2.125 + weight_arrays(H, V.v)));
-        launch_restrict<T>(H, V.v, f, V.c, C.rhs);
-    }
+    cycle_pre(H, V, l, nu, f, V.c, C.rhs);
     T* e;
     T wc;
     if (C.kcyc) {
@@ -933,34 +996,7 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
         e = mgcycle(H, Hh, l + 1, C.rhs, 0, (const T*)nullptr);
         wc = (T)H->prm.wc;
     }
-    if (nu == 1 && H->prm.pfuse && fused(H, sizeof(T), V.n)) {
-        // reads x, f, the weights (or the density), the coarse correction and q for the dot;
-        // writes z
-        const Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
-        dim3 grid;
-        {
-            TimeScope ts(H, fine ? kid<T>(KT_PROLONG_HALF) : -1,
-                         (double)V.n * ((3.125 + weight_arrays(H, V.v)) * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
-            if (ndot == 0) grid = launch_prolong_half<T, 0, TQ>(H, V.v, f, V.c, e, wc, V.c2, q, R);
-            else if (ndot == 1) grid = launch_prolong_half<T, 1, TQ>(H, V.v, f, V.c, e, wc, V.c2, q, R);
-            else grid = launch_prolong_half<T, 2, TQ>(H, V.v, f, V.c, e, wc, V.c2, q, R);
-        }
-        if (ndot > 0) finish(H, R, grid, ndot);
-        return V.c2;
-    }
-    {
-        // reads x, f, the weights (or the density) and the coarse correction (the per-cell
-        // kernels also 1/D); writes y
-        TimeScope ts(H, fine ? kid<T>(KT_PROLONG_BLACK) : -1,
-                     (double)V.n * sizeof(T) * (3.125 + invd_arrays(H) + weight_arrays(H, V.v)));
-        launch_prolong_black<T>(H, V.v, f, V.c, e, wc, V.c2);
-    }
-    T* cur = V.c2;
-    for (int s = 0; s < nu; ++s) {
-        if (s > 0) smooth_half(H, V, fine, f, cur, 1, 0, (const T*)nullptr, l);
-        smooth_half(H, V, fine, f, cur, 0, (s == nu - 1) ? ndot : 0, q, l);
-    }
-    return cur;
+    return cycle_post(H, V, l, nu, f, V.c, e, wc, V.c2, ndot, q);
 }
 
 template <class T>
@@ -1372,6 +1408,76 @@ static int guarded(pp_handle h, F&& f)
     }
 }
 
+// Relative residual ||bbar - A p|| / ||bbar|| of step 11 on the device:
+// density check, sum of b, then the two squared norms by the plane-marching
+// operator, each reduction through `partials` (kMaxPartialBlocks * kMaxRed
+// doubles) into `slots` (8 doubles).  Synchronises `st`.
+enum : int { R_RHOSUM = 0, R_RHOBAD, R_BSUM, R_BBAD, R_RR, R_BB, kRelSlots = 8 };
+static int rel_residual_on(hipStream_t st, int nx, int ny, int nz, double h, const double* rho, const double* rhs,
+                           const double* p, double* rel_out, double* partials, double* slots)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    auto R = [&](int a, int b) {
+        Reduce r;
+        r.partials = partials;
+        r.out = slots;
+        r.slot[0] = a; r.slot[1] = b; r.slot[2] = 0; r.slot[3] = 0;
+        return r;
+    };
+    const dim3 lg = lin_grid(n);
+    k_sum_check<<<lg, kBlock, 0, st>>>((int)n, rho, 1, R(R_RHOSUM, R_RHOBAD));
+    check_launch();
+    k_reduce_finish<<<1, kBlock, 0, st>>>(R(R_RHOSUM, R_RHOBAD), (int)(lg.x * lg.y * lg.z), 2);
+    check_launch();
+    k_sum_check<<<lg, kBlock, 0, st>>>((int)n, rhs, 0, R(R_BSUM, R_BBAD));
+    check_launch();
+    k_reduce_finish<<<1, kBlock, 0, st>>>(R(R_BSUM, R_BBAD), (int)(lg.x * lg.y * lg.z), 2);
+    check_launch();
+    const MGeo g = mgeo(nx, ny, nz, 64, false, 512, kMarchThreads<double, true>);
+    const LevelView<double> v{nx, ny, nz, nullptr, nullptr, nullptr, nullptr, rho};
+    with_bx(g.bx, [&](auto B) {
+        m_rel_residual<decltype(B)::value><<<g.grid, g.block, 0, st>>>(v, p, rhs, 1.0 / (h * h),
+                                                                       Coefs{slots, R_BSUM, -1, 1.0 / (double)n}, g.kper,
+                                                                       R(R_RR, R_BB));
+    });
+    check_launch();
+    k_reduce_finish<<<1, kBlock, 0, st>>>(R(R_RR, R_BB), (int)(g.grid.x * g.grid.y * g.grid.z), 2);
+    check_launch();
+    double host[kRelSlots];
+    PP_HIP(hipMemcpyAsync(host, slots, sizeof(host), hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    if (host[R_RHOBAD] != 0.0) throw Fail(PP_ERR_NONFINITE, "density not finite or not > 0");
+    if (host[R_BBAD] != 0.0) throw Fail(PP_ERR_NONFINITE, "rhs not finite");
+    const double rr = std::sqrt(host[R_RR]), bb = std::sqrt(host[R_BB]);
+    *rel_out = bb > 0.0 ? rr / bb : (rr > 0.0 ? HUGE_VAL : 0.0);
+    return PP_OK;
+}
+
+// Checks of the residual entry points: sizes, pointers, and a launch whose
+// partial sums fit the kMaxPartialBlocks partials.
+static int rel_residual_args(int nx, int ny, int nz, double h, const void* rho, const void* rhs, const void* p,
+                             const void* rel_out)
+{
+    if (!rho || !rhs || !p || !rel_out) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !std::isfinite(h)) { g_thread_err = "bad sizes or h"; return PP_ERR_INVALID; }
+    if ((size_t)nx * ny * nz + (size_t)nx * ny > (size_t)INT_MAX) {
+        g_thread_err = "grid too large (32-bit cell indices)";
+        return PP_ERR_INVALID;
+    }
+    const MGeo g = mgeo(nx, ny, nz, 64, false, 512, kMarchThreads<double, true>);
+    if ((size_t)g.grid.x * g.grid.y * g.grid.z > (size_t)kMaxPartialBlocks) {
+        g_thread_err = "cross-section too large: more than 4096 tiles of 64 x 8 cells per plane";
+        return PP_ERR_INVALID;
+    }
+    return PP_OK;
+}
+
+// Handle-less stencil entry points index cells with 32-bit ints.
+static bool grid_fits_int(int nx, int ny, int nz)
+{
+    return (size_t)nx * ny * nz + (size_t)nx * ny <= (size_t)INT_MAX;
+}
+
 extern "C" {
 
 const char* pp_version(void) { return "ppsolve 0.1 (gfx950)"; }
@@ -1484,11 +1590,83 @@ int pp_apply(pp_handle h, const double* x, double* y)
         Handle* H = &h->h;
         PP_HIP(hipSetDevice(H->device));
         enter(H);
-        Geo g = geo(H->cfg.nx, H->cfg.ny, H->cfg.nz);
-        const LevelView<double> v{H->cfg.nx, H->cfg.ny, H->cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
-        k_apply_a<<<g.grid, g.block, 0, H->stream>>>(v, 1.0 / (H->cfg.h * H->cfg.h), x, y, g.kper);
+        const double inv_h2 = 1.0 / (H->cfg.h * H->cfg.h);
+        if (H->prm.march) {
+            // the finest-level operator exactly as the solve's passes form it
+            const LevelView<double> v = fine64(H);
+            const MGeo g = march_geo(H, v, H->prm.mbx);
+            with_bx(g.bx, [&](auto B) {
+                with_rho(v, [&](auto W) {
+                    m_apply<decltype(B)::value, decltype(W)::value>
+                        <<<g.grid, g.block, 0, H->stream>>>(v, x, y, inv_h2, g.kper, xcd_of(H, v));
+                });
+            });
+        } else {
+            Geo g = geo(H->cfg.nx, H->cfg.ny, H->cfg.nz);
+            const LevelView<double> v{H->cfg.nx, H->cfg.ny, H->cfg.nz, H->c64[0].wx, H->c64[0].wy, H->c64[0].wz, nullptr};
+            k_apply_a<<<g.grid, g.block, 0, H->stream>>>(v, inv_h2, x, y, g.kper);
+        }
         check_launch();
         leave(H);
+        PP_HIP(hipStreamSynchronize(H->stream));
+        return PP_OK;
+    });
+}
+
+// Common checks of the cycle-leg entry points; the finest level must coarsen.
+static int leg_checks(pp_handle h, bool ok_ptrs)
+{
+    if (!h) { g_thread_err = "null handle"; return PP_ERR_INVALID; }
+    if (!ok_ptrs) { h->h.err = "null array"; return PP_ERR_INVALID; }
+    if (!h->h.have_density) { h->h.err = "cycle pass before pp_set_density"; return PP_ERR_STATE; }
+    if (h->h.nlev < 2) { h->h.err = "the grid does not coarsen (nx, ny even, nz divisible by 4, more than 64 cells)"; return PP_ERR_INVALID; }
+    return PP_OK;
+}
+
+int pp_presmooth_restrict(pp_handle h, const void* f, void* x, void* rc)
+{
+    if (int e = leg_checks(h, f && x && rc)) return e;
+    return guarded(h, [&]() -> int {
+        Handle* H = &h->h;
+        PP_HIP(hipSetDevice(H->device));
+        enter(H);
+        if (H->cfg.mode == PP_FP64) {
+            Lev<double>& V = H->h64.L[0];
+            cycle_pre<double>(H, V, 0, sweeps_of(H, V, 0), (const double*)f, (double*)x, (double*)rc);
+        } else {
+            Lev<float>& V = H->h32.L[0];
+            cycle_pre<float>(H, V, 0, sweeps_of(H, V, 0), (const float*)f, (float*)x, (float*)rc);
+        }
+        leave(H);
+        PP_HIP(hipStreamSynchronize(H->stream));
+        return PP_OK;
+    });
+}
+
+int pp_prolong_postsmooth(pp_handle h, const void* f, const void* x, const void* e, double wc, void* z, const double* q,
+                          double* dots)
+{
+    if (int st = leg_checks(h, f && x && e && z && (!q || dots))) return st;
+    return guarded(h, [&]() -> int {
+        Handle* H = &h->h;
+        PP_HIP(hipSetDevice(H->device));
+        enter(H);
+        const int ndot = q ? 2 : 0;
+        if (H->cfg.mode == PP_FP64) {
+            Lev<double>& V = H->h64.L[0];
+            cycle_post<double, double>(H, V, 0, sweeps_of(H, V, 0), (const double*)f, (const double*)x, (const double*)e,
+                                       wc, (double*)z, ndot, q);
+        } else {
+            Lev<float>& V = H->h32.L[0];
+            cycle_post<float, double>(H, V, 0, sweeps_of(H, V, 0), (const float*)f, (const float*)x, (const float*)e,
+                                      (float)wc, (float*)z, ndot, q);
+        }
+        leave(H);
+        if (q) {
+            read_slots(H, lslot(0, 0), kLevSlots);
+            dots[0] = H->host_slots[lslot(0, S_SUMZ)];
+            dots[1] = H->host_slots[lslot(0, S_ZQ)];
+        }
         PP_HIP(hipStreamSynchronize(H->stream));
         return PP_OK;
     });
@@ -1564,7 +1742,10 @@ int pp_divergence(int nx, int ny, int nz, double h, double dt, const double* u, 
                   void* hip_stream)
 {
     if (!u || !v || !w || !out) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
-    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !(dt > 0.0)) { g_thread_err = "bad sizes, h or dt"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !(dt > 0.0) || !grid_fits_int(nx, ny, nz)) {
+        g_thread_err = "bad sizes, h or dt";
+        return PP_ERR_INVALID;
+    }
     return guarded(nullptr, [&]() -> int {
         Geo g = geo(nx, ny, nz, 8192);
         k_divergence<<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h * dt, u, v, w, out, g.kper);
@@ -1578,7 +1759,10 @@ int pp_project(int nx, int ny, int nz, double h, double dt, const double* rho, c
                void* hip_stream)
 {
     if (!rho || !p || !u || !v || !w) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
-    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !(dt > 0.0)) { g_thread_err = "bad sizes, h or dt"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !(dt > 0.0) || !grid_fits_int(nx, ny, nz)) {
+        g_thread_err = "bad sizes, h or dt";
+        return PP_ERR_INVALID;
+    }
     return guarded(nullptr, [&]() -> int {
         Geo g = geo(nx, ny, nz, 8192);
         k_project<<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h, dt, rho, p, u, v, w, g.kper);
@@ -1588,11 +1772,37 @@ int pp_project(int nx, int ny, int nz, double h, double dt, const double* rho, c
     });
 }
 
+int pp_rel_residual(int nx, int ny, int nz, double h, const double* rho, const double* rhs, const double* p, double* rel_out,
+                    void* hip_stream)
+{
+    if (int e = rel_residual_args(nx, ny, nz, h, rho, rhs, p, rel_out)) return e;
+    double* buf = nullptr;
+    const size_t bytes = sizeof(double) * ((size_t)kMaxPartialBlocks * kMaxRed + kRelSlots);
+    int rc = guarded(nullptr, [&]() -> int {
+        hipError_t e = hipMalloc((void**)&buf, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            buf = nullptr;
+            throw Fail(PP_ERR_OOM, "hipMalloc of the residual's partial sums failed");
+        }
+        return rel_residual_on((hipStream_t)hip_stream, nx, ny, nz, h, rho, rhs, p, rel_out, buf,
+                               buf + (size_t)kMaxPartialBlocks * kMaxRed);
+    });
+    if (buf) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
+        (void)hipFree(buf);
+    }
+    return rc;
+}
+
 int pp_surface_tension_rhs(int nx, int ny, int nz, double h, double sigma, const double* rho, const double* alpha,
                            const double* kappa, double* out, void* hip_stream)
 {
     if (!rho || !alpha || !kappa || !out) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
-    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0)) { g_thread_err = "bad sizes or h"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !grid_fits_int(nx, ny, nz)) {
+        g_thread_err = "bad sizes or h";
+        return PP_ERR_INVALID;
+    }
     return guarded(nullptr, [&]() -> int {
         Geo g = geo(nx, ny, nz, 8192);
         k_surface_rhs<<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h, sigma, rho, alpha, kappa, out, g.kper);

@@ -28,9 +28,10 @@ _NAMES = {0: "PP_OK", -1: "PP_ERR_INVALID", -2: "PP_ERR_OOM", -3: "PP_ERR_NOT_CO
 MODES = {"fp64": 0, "fp32_refined": 1}
 
 # Every entry point declared in include/pp.h.
-EXPORTS = ("pp_footprint_bytes", "pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_destroy",
+EXPORTS = ("pp_footprint_bytes", "pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_presmooth_restrict",
+           "pp_prolong_postsmooth", "pp_destroy",
            "pp_last_error", "pp_density_from_fraction", "pp_divergence", "pp_project", "pp_surface_tension_rhs",
-           "pp_kernel_timing", "pp_version")
+           "pp_rel_residual", "pp_kernel_timing", "pp_version")
 
 
 class PPError(RuntimeError):
@@ -78,6 +79,8 @@ def lib():
         L.pp_set_density.argtypes = [vp, vp]
         L.pp_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Stats)]
         L.pp_apply.argtypes = [vp, vp, vp]
+        L.pp_presmooth_restrict.argtypes = [vp, vp, vp, vp]
+        L.pp_prolong_postsmooth.argtypes = [vp, vp, vp, vp, cd, vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.pp_destroy.argtypes = [vp]
         L.pp_last_error.argtypes = [vp]
         L.pp_last_error.restype = ctypes.c_char_p
@@ -86,9 +89,12 @@ def lib():
         L.pp_version.restype = ctypes.c_char_p
         L.pp_project.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp, vp]
         L.pp_surface_tension_rhs.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp]
+        L.pp_rel_residual.argtypes = [ci, ci, ci, cd, vp, vp, vp, ctypes.POINTER(cd), vp]
+        L.pp_rel_residual.restype = ci
         L.pp_kernel_timing.argtypes = [vp, ci, ctypes.POINTER(KernelTime), ci]
         L.pp_kernel_timing.restype = ci
-        for name in ("pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_destroy",
+        for name in ("pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_presmooth_restrict",
+                     "pp_prolong_postsmooth", "pp_destroy",
                      "pp_density_from_fraction", "pp_divergence", "pp_project", "pp_surface_tension_rhs"):
             getattr(L, name).restype = ci
         _lib = L
@@ -161,6 +167,42 @@ class Solver:
             y = torch.empty_like(x)
         _check(lib().pp_apply(self._h, _dev(x, self.n, "x"), _dev(y, self.n, "y")), self._h)
         return y
+
+    @property
+    def cycle_dtype(self):
+        """Precision of the multigrid cycle's arrays (float64, or float32 in the refined form)."""
+        return torch.float64 if self.cfg.mode == MODES["fp64"] else torch.float32
+
+    def _cyc(self, t: torch.Tensor, n: int, name: str):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.cycle_dtype:
+            raise TypeError(f"{name} must be a {self.cycle_dtype} CUDA tensor")
+        if not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be contiguous with {n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _coarse_n(self):
+        nz, ny, nx = self.shape
+        return (nz // 2) * (ny // 2) * (nx // 2)
+
+    def presmooth_restrict(self, f: torch.Tensor):
+        """Down leg of the finest-level cycle: returns (x, rc)."""
+        nz, ny, nx = self.shape
+        x = torch.empty_like(f)
+        rc = torch.empty((nz // 2, ny // 2, nx // 2), dtype=f.dtype, device=f.device)
+        _check(lib().pp_presmooth_restrict(self._h, self._cyc(f, self.n, "f"), self._cyc(x, self.n, "x"),
+                                           self._cyc(rc, rc.numel(), "rc")), self._h)
+        return x, rc
+
+    def prolong_postsmooth(self, f: torch.Tensor, x: torch.Tensor, e: torch.Tensor, wc: float = 1.0,
+                           q: torch.Tensor | None = None):
+        """Up leg of the finest-level cycle: returns z, or (z, (sum z, <z, q>)) with q."""
+        z = torch.empty_like(f)
+        dots = (ctypes.c_double * 2)()
+        _check(lib().pp_prolong_postsmooth(self._h, self._cyc(f, self.n, "f"), self._cyc(x, self.n, "x"),
+                                           self._cyc(e, self._coarse_n(), "e"), float(wc), self._cyc(z, self.n, "z"),
+                                           _dev(q, self.n, "q") if q is not None else None,
+                                           dots if q is not None else None), self._h)
+        return (z, (dots[0], dots[1])) if q is not None else z
 
     def timing(self, mode: int):
         """mode 1: start (clear), -1: stop, 0: return {name: (total_ms, launches, bytes)}."""
@@ -235,3 +277,14 @@ def surface_tension_rhs(rho: torch.Tensor, alpha: torch.Tensor, kappa: torch.Ten
 class Result:
     p: torch.Tensor
     stats: dict
+
+
+def rel_residual(rho: torch.Tensor, rhs: torch.Tensor, p: torch.Tensor, h: float, stream=None) -> float:
+    """||bbar - A p|| / ||bbar|| on the device (pp_rel_residual)."""
+    nz, ny, nx = rho.shape
+    n = rho.numel()
+    out = ctypes.c_double()
+    fn = lib().pp_rel_residual
+    _check(fn(nx, ny, nz, float(h), _dev(rho, n, "rho"), _dev(rhs, n, "rhs"), _dev(p, n, "p"), ctypes.byref(out),
+              _stream_ptr(stream)))
+    return out.value

@@ -55,3 +55,16 @@ def test_create_rejects_bad_config_without_gpu():
     rc = ppsolve.lib().pp_create(ctypes.byref(cfg), None, ctypes.byref(h))
     assert rc == ppsolve.PP_ERR_INVALID and not h.value
     assert b"even" in ppsolve.lib().pp_last_error(None)
+
+
+def test_grid_beyond_32_bit_indices_is_rejected():
+    """Cells are indexed with 32-bit ints: a grid whose last index plus one plane
+    does not fit (2^31 cells here) is refused before anything is allocated."""
+    import ctypes
+    for shape in [(1024, 1024, 2048), (2048, 2048, 512)]:
+        assert ppsolve.footprint_bytes(*shape) == 0
+        cfg = ppsolve.make_config(*shape)
+        h = ctypes.c_void_p()
+        rc = ppsolve.lib().pp_create(ctypes.byref(cfg), None, ctypes.byref(h))
+        assert rc == ppsolve.PP_ERR_INVALID and not h.value
+        assert b"32-bit" in ppsolve.lib().pp_last_error(None)
