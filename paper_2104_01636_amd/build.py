@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libppsolve.so")
-SOURCES = ["pp_solver.hip", "pp_server.cpp"]
+SOURCES = ["pp_solver.hip", "pp_server.cpp", "pp_server_hip.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -14,11 +14,11 @@
 // stream).  A request larger than the whole budget is rejected (PP_ERR_OOM).
 //
 // The device work is behind a small backend table so the scheduler can be
-// exercised on the host with a fake backend.
+// exercised on the host with a fake backend; the HIP backend is in
+// pp_server_hip.cpp, and this file uses no HIP itself (it builds with a plain
+// host compiler, which the sanitizer builds of the scheduler rely on).
 #include "../../include/pp.h"
 #include "../../include/pp_server.h"
-
-#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
@@ -33,6 +33,9 @@
 #include <thread>
 #include <vector>
 
+// The HIP library's backend (pp_server_hip.cpp).
+pp_backend ppsrv_hip_backend();
+
 namespace {
 
 double now_s()
@@ -40,80 +43,6 @@ double now_s()
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
-
-// ---------------------------------------------------------------- HIP backend
-
-struct HipCase {
-    pp_handle h = nullptr;
-    hipStream_t stream = nullptr;
-    double* p = nullptr;
-    size_t n = 0;
-};
-
-size_t hip_footprint(void*, const pp_config* cfg)
-{
-    size_t b = pp_footprint_bytes(cfg);
-    if (b == 0) return 0;
-    return b + (size_t)cfg->nx * cfg->ny * cfg->nz * sizeof(double) + 4096;
-}
-
-int hip_open(void*, const pp_config* cfg, void** out)
-{
-    auto* c = new HipCase;
-    c->n = (size_t)cfg->nx * cfg->ny * cfg->nz;
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-        delete c;
-        return PP_ERR_HIP;
-    }
-    if (hipMalloc((void**)&c->p, c->n * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipStreamDestroy(c->stream);
-        delete c;
-        return PP_ERR_OOM;
-    }
-    if (hipMemsetAsync(c->p, 0, c->n * sizeof(double), c->stream) != hipSuccess) {
-        (void)hipFree(c->p);
-        (void)hipStreamDestroy(c->stream);
-        delete c;
-        return PP_ERR_HIP;
-    }
-    int rc = pp_create(cfg, c->stream, &c->h);
-    if (rc != PP_OK) {
-        (void)hipFree(c->p);
-        (void)hipStreamDestroy(c->stream);
-        delete c;
-        return rc;
-    }
-    *out = c;
-    return PP_OK;
-}
-
-int hip_set_density(void*, void* cs, const double* rho) { return pp_set_density(static_cast<HipCase*>(cs)->h, rho); }
-
-int hip_solve(void*, void* cs, const double* rhs, double* p_out, pp_stats* st)
-{
-    auto* c = static_cast<HipCase*>(cs);
-    int rc = pp_solve(c->h, rhs, c->p, st);
-    if (p_out && (rc == PP_OK || rc == PP_ERR_NOT_CONVERGED)) {
-        if (hipMemcpyAsync(p_out, c->p, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-            return PP_ERR_HIP;
-        if (hipStreamSynchronize(c->stream) != hipSuccess) return PP_ERR_HIP;
-    }
-    return rc;
-}
-
-void hip_close(void*, void* cs)
-{
-    auto* c = static_cast<HipCase*>(cs);
-    if (!c) return;
-    pp_destroy(c->h);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->p) (void)hipFree(c->p);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
-    delete c;
-}
-
-const char* hip_error(void*, void* cs) { return cs ? pp_last_error(static_cast<HipCase*>(cs)->h) : pp_last_error(nullptr); }
 
 // ---------------------------------------------------------------- scheduler
 
@@ -158,7 +87,11 @@ struct pp_server_s {
     std::deque<std::shared_ptr<Request>> queue;
     std::map<long long, std::shared_ptr<Request>> reqs;
     std::map<long long, std::unique_ptr<Case>> cases;
-    size_t resident = 0, peak_resident = 0;
+    // resident: bytes of the cases in the map and of evicted cases not yet closed
+    // (what the device holds); pending: bytes of admitted new cases whose
+    // evictions are still being closed (not opened yet).  Admission keeps
+    // resident + pending within the budget, so resident never exceeds it.
+    size_t resident = 0, pending = 0, peak_resident = 0;
     long long next_id = 1;
     long long evictions = 0, rejected = 0, completed = 0;
     int running = 0, max_running = 0;
@@ -182,14 +115,14 @@ struct pp_server_s {
             }
             size_t need = be.footprint(be.ctx, &r.cfg);
             if (need > cfg.budget_bytes) return (int)qi;  // rejected by the worker
-            if (resident + need <= cfg.budget_bytes) return (int)qi;
+            if (resident + pending + need <= cfg.budget_bytes) return (int)qi;
             // evict idle cases, least recently used first, if that makes room
             size_t idle = 0;
             for (auto& kv : cases)
                 if (!kv.second->busy && !kv.second->opening) idle += kv.second->bytes;
-            if (resident - idle + need > cfg.budget_bytes) continue;  // must wait for running cases
+            if (resident + pending - idle + need > cfg.budget_bytes) continue;  // must wait for running cases
             size_t freed = 0;
-            while (resident - freed + need > cfg.budget_bytes) {
+            while (resident + pending - freed + need > cfg.budget_bytes) {
                 Case* lru = nullptr;
                 for (auto& kv : cases) {
                     Case* c = kv.second.get();
@@ -266,14 +199,16 @@ struct pp_server_s {
                 nc->opening = true;
                 c = nc.get();
                 cases[r->case_id] = std::move(nc);
-                // the new case's bytes are counted before the evicted ones are returned, so
-                // no other slot can admit into memory that is not free yet
-                resident += need;
                 fresh = true;
                 c->busy = true;
                 ++running;
                 max_running = std::max(max_running, running);
+                // the new case is pending while the evicted ones close, so no other slot
+                // can admit into memory that is not free yet
+                pending += need;
                 close_evicted(lk, evict);
+                pending -= need;
+                resident += need;
                 peak_resident = std::max(peak_resident, resident);
             } else {
                 c = it->second.get();
@@ -345,7 +280,7 @@ int pp_server_create(const pp_server_config* cfg, const pp_backend* backend, pp_
     if (backend) {
         s->be = *backend;
     } else {
-        s->be = pp_backend{nullptr, hip_footprint, hip_open, hip_set_density, hip_solve, hip_close, hip_error};
+        s->be = ppsrv_hip_backend();
     }
     for (int i = 0; i < cfg->slots; ++i) s->workers.emplace_back([s] { s->worker(); });
     *out = s;
