@@ -190,6 +190,18 @@ int pp_surface_tension_rhs(int nx, int ny, int nz, double h, double sigma, const
 int pp_rel_residual(int nx, int ny, int nz, double h, const double* rho, const double* rhs, const double* p, double* rel_out,
                     void* hip_stream);
 
+/* pp_rel_residual without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels, result and errors.  Its
+ * partial sums live in a fixed static device array of 131136 bytes per GPU
+ * (held until the process ends); grids needing more partial sums than it holds
+ * (more than 4096 tiles of 64 x 8 cells per plane) are rejected with
+ * PP_ERR_INVALID.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (different host threads or streams) race and must be serialised
+ * by the caller.  Call it with the device of hip_stream current. */
+int pp_rel_residual_noalloc(int nx, int ny, int nz, double h, const double* rho, const double* rhs, const double* p,
+                            double* rel_out, void* hip_stream);
+
 /* Device time of the finest-level kernels, measured with HIP events on the
  * handle's stream around each launch.
  *   mode = 1: clear the counters and start timing;

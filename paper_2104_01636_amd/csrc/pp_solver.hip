@@ -41,6 +41,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1472,6 +1473,35 @@ static int rel_residual_args(int nx, int ny, int nz, double h, const void* rho, 
     return PP_OK;
 }
 
+// Scratch of pp_rel_residual_noalloc: the partial sums and result slots of its
+// reductions (131136 bytes).  Every GPU the library runs on holds its own copy
+// until the process ends, and every call on that GPU shares it.  Host code uses
+// the per-device address from hipGetSymbolAddress, never this name.
+static __device__ __align__(256) double scratch[(size_t)kMaxPartialBlocks * kMaxRed + kRelSlots];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+static double* scratch_of_current_device()
+{
+    int dev = -1;
+    PP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Fail(PP_ERR_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            throw Fail(PP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
 // Handle-less stencil entry points index cells with 32-bit ints.
 static bool grid_fits_int(int nx, int ny, int nz)
 {
@@ -1793,6 +1823,17 @@ int pp_rel_residual(int nx, int ny, int nz, double h, const double* rho, const d
         (void)hipFree(buf);
     }
     return rc;
+}
+
+int pp_rel_residual_noalloc(int nx, int ny, int nz, double h, const double* rho, const double* rhs, const double* p,
+                            double* rel_out, void* hip_stream)
+{
+    if (int e = rel_residual_args(nx, ny, nz, h, rho, rhs, p, rel_out)) return e;
+    return guarded(nullptr, [&]() -> int {
+        double* buf = scratch_of_current_device();
+        return rel_residual_on((hipStream_t)hip_stream, nx, ny, nz, h, rho, rhs, p, rel_out, buf,
+                               buf + (size_t)kMaxPartialBlocks * kMaxRed);
+    });
 }
 
 int pp_surface_tension_rhs(int nx, int ny, int nz, double h, double sigma, const double* rho, const double* alpha,

@@ -31,7 +31,7 @@ MODES = {"fp64": 0, "fp32_refined": 1}
 EXPORTS = ("pp_footprint_bytes", "pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_presmooth_restrict",
            "pp_prolong_postsmooth", "pp_destroy",
            "pp_last_error", "pp_density_from_fraction", "pp_divergence", "pp_project", "pp_surface_tension_rhs",
-           "pp_rel_residual", "pp_kernel_timing", "pp_version")
+           "pp_rel_residual", "pp_rel_residual_noalloc", "pp_kernel_timing", "pp_version")
 
 
 class PPError(RuntimeError):
@@ -91,6 +91,8 @@ def lib():
         L.pp_surface_tension_rhs.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp]
         L.pp_rel_residual.argtypes = [ci, ci, ci, cd, vp, vp, vp, ctypes.POINTER(cd), vp]
         L.pp_rel_residual.restype = ci
+        L.pp_rel_residual_noalloc.argtypes = [ci, ci, ci, cd, vp, vp, vp, ctypes.POINTER(cd), vp]
+        L.pp_rel_residual_noalloc.restype = ci
         L.pp_kernel_timing.argtypes = [vp, ci, ctypes.POINTER(KernelTime), ci]
         L.pp_kernel_timing.restype = ci
         for name in ("pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_presmooth_restrict",
@@ -279,12 +281,13 @@ class Result:
     stats: dict
 
 
-def rel_residual(rho: torch.Tensor, rhs: torch.Tensor, p: torch.Tensor, h: float, stream=None) -> float:
-    """||bbar - A p|| / ||bbar|| on the device (pp_rel_residual)."""
+def rel_residual(rho: torch.Tensor, rhs: torch.Tensor, p: torch.Tensor, h: float, stream=None,
+                 noalloc: bool = False) -> float:
+    """||bbar - A p|| / ||bbar|| on the device (pp_rel_residual, or pp_rel_residual_noalloc)."""
     nz, ny, nx = rho.shape
     n = rho.numel()
     out = ctypes.c_double()
-    fn = lib().pp_rel_residual
+    fn = lib().pp_rel_residual_noalloc if noalloc else lib().pp_rel_residual
     _check(fn(nx, ny, nz, float(h), _dev(rho, n, "rho"), _dev(rhs, n, "rhs"), _dev(p, n, "p"), ctypes.byref(out),
               _stream_ptr(stream)))
     return out.value
