@@ -201,6 +201,44 @@ def project(rho, p, u, v, w, h, dt=1.0):
     return un, vn, wn
 
 
+def face_to_cell(fx, fy, fz):
+    """Linear average of the two faces that bound a cell along each axis (the
+    face-to-cell counterpart of the linear cell-to-face averaging defined in the
+    note after the step list of Section 2.2).  Face arrays use the +face layout:
+    the west face of cell i is the +x face of cell i-1, and the wall faces
+    (i = -1/2, i = nx-1/2 and likewise in y) carry zero; z is periodic."""
+    fx = np.array(fx, dtype=np.float64, copy=True)
+    fy = np.array(fy, dtype=np.float64, copy=True)
+    fz = np.asarray(fz, dtype=np.float64)
+    fx[:, :, -1] = 0.0
+    fy[:, -1, :] = 0.0
+    wx = np.zeros_like(fx)
+    wx[:, :, 1:] = fx[:, :, :-1]
+    sy = np.zeros_like(fy)
+    sy[:, 1:, :] = fy[:, :-1, :]
+    bz = np.roll(fz, 1, axis=0)
+    return 0.5 * (wx + fx), 0.5 * (sy + fy), 0.5 * (bz + fz)
+
+
+def correct_cell_velocity(rho, p, pt, uc, vc, wc, h, dt=1.0):
+    """Step 12 of Section 2.2 on the cell-centred velocity:
+
+        u_c <- uhat_c - dt * (grad(p)/rho + grad(pt)/rho)_{f->c}
+
+    with the face terms beta_f (p_R - p_L)/h + beta_f (pt_R - pt_L)/h (beta_f =
+    1/rho_f, rho_f the linear average; zero on the walls), averaged to the cell
+    by face_to_cell.  pt (the surface-tension pressure of step 6) may be None."""
+    bx, by, bz = face_coefficients(rho)
+    gx, gy, gz = gradient(p, h)
+    fx, fy, fz = bx * gx, by * gy, bz * gz
+    if pt is not None:
+        tx, ty, tz = gradient(pt, h)
+        fx, fy, fz = fx + bx * tx, fy + by * ty, fz + bz * tz
+    ax, ay, az = face_to_cell(fx, fy, fz)
+    return (np.asarray(uc, dtype=np.float64) - dt * ax, np.asarray(vc, dtype=np.float64) - dt * ay,
+            np.asarray(wc, dtype=np.float64) - dt * az)
+
+
 def surface_force(alpha_gas, kappa, sigma, h):
     """Sharp-surface-force face values (Section 2.1, eq. jump_condition, with the
     jump applied at faces): f_f = sigma * kappa_f * (a_R - a_L) / h, kappa_f the

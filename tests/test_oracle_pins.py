@@ -453,3 +453,65 @@ def test_static_bubble_exact_curvature_balances_to_machine_zero():
     spurious = max(np.max(np.abs(bx * (fx - gx))), np.max(np.abs(by * (fy - gy))), np.max(np.abs(bz * (fz - gz))))
     scale = np.max(np.abs(bx * fx))
     assert spurious < 1e-9 * scale
+
+
+# ------------------------------------------------------------------ step 12 on cells
+
+def test_face_to_cell_closed_forms():
+    """A constant face field averages to itself away from the walls and to half of
+    itself in the cells on a wall (the wall face carries zero); a linear face
+    field averages to its value at the cell centre."""
+    nz, ny, nx = 6, 5, 7
+    one = np.ones((nz, ny, nx))
+    ax, ay, az = P.face_to_cell(3.0 * one, -2.0 * one, 0.5 * one)
+    np.testing.assert_array_equal(az, 0.5 * one)                      # z periodic: no walls
+    np.testing.assert_array_equal(ax[:, :, 1:-1], 3.0 * one[:, :, 1:-1])
+    np.testing.assert_array_equal(ax[:, :, 0], 1.5 * one[:, :, 0])
+    np.testing.assert_array_equal(ax[:, :, -1], 1.5 * one[:, :, -1])
+    np.testing.assert_array_equal(ay[:, 1:-1, :], -2.0 * one[:, 1:-1, :])
+    np.testing.assert_array_equal(ay[:, 0, :], -1.0 * one[:, 0, :])
+    # face value = position of the face (i + 1) along x: the average is the centre i + 1/2
+    xf = np.broadcast_to(np.arange(nx) + 1.0, (nz, ny, nx))
+    ax, _, _ = P.face_to_cell(xf, 0 * one, 0 * one)
+    np.testing.assert_allclose(ax[:, :, 1:-1], (np.arange(nx) + 0.5)[1:-1] * one[:, :, 1:-1], rtol=0, atol=1e-15)
+
+
+def test_cell_correction_linear_pressure_and_density_scaling():
+    """A pressure linear in z with uniform density gives a uniform face gradient
+    beta G away from the seam; every cell away from it is corrected by exactly
+    dt * G / rho in w and not at all in u, v.  Splitting the pressure between p
+    and pt gives the same correction, and a density c times larger gives a
+    correction c times smaller."""
+    nz, ny, nx, h, dt, rho0 = 8, 4, 5, 0.25, 0.5, 4.0
+    z = (np.arange(nz) + 0.5) * h
+    p = np.broadcast_to((3.0 * z)[:, None, None], (nz, ny, nx)).copy()
+    rho = np.full((nz, ny, nx), rho0)
+    uc, vc, wc = (np.random.default_rng(k).standard_normal((nz, ny, nx)) for k in range(3))
+    un, vn, wn = P.correct_cell_velocity(rho, p, None, uc, vc, wc, h, dt)
+    np.testing.assert_array_equal(un, uc)
+    np.testing.assert_array_equal(vn, vc)
+    inner = slice(1, nz - 1)   # the faces at the periodic seam see the jump of the linear ramp
+    np.testing.assert_allclose(wn[inner], wc[inner] - dt * 3.0 / rho0, rtol=0, atol=1e-14)
+    un2, vn2, wn2 = P.correct_cell_velocity(rho, 0.25 * p, 0.75 * p, uc, vc, wc, h, dt)
+    np.testing.assert_allclose(wn2, wn, rtol=0, atol=1e-14)
+    _, _, wn3 = P.correct_cell_velocity(10.0 * rho, p, None, uc, vc, wc, h, dt)
+    np.testing.assert_allclose(wc - wn3, 0.1 * (wc - wn), rtol=1e-13, atol=1e-15)
+
+
+def test_cell_correction_agrees_with_face_projection():
+    """The cell correction is the face-to-cell average of the face projection's
+    correction: (u_f - P.project(u_f))_{f->c} == uhat_c - correct_cell_velocity(uhat_c)
+    for pt = 0, on a grid with density jumps."""
+    case = W.random_small_case(9, 6, 5, 8)
+    rho = P.density_from_fraction(case.alpha)
+    p = np.random.default_rng(3).standard_normal(rho.shape)
+    un, vn, wn = P.project(rho, p, case.u, case.v, case.w, case.h, dt=0.3)
+    du, dv, dw = case.u - un, case.v - vn, case.w - wn
+    du[:, :, -1] = 0.0
+    dv[:, -1, :] = 0.0
+    ax, ay, az = P.face_to_cell(du, dv, dw)
+    zero = np.zeros_like(rho)
+    cu, cv, cw = P.correct_cell_velocity(rho, p, None, zero, zero, zero, case.h, dt=0.3)
+    np.testing.assert_allclose(-cu, ax, rtol=0, atol=1e-12 * np.abs(ax).max())
+    np.testing.assert_allclose(-cv, ay, rtol=0, atol=1e-12 * np.abs(ay).max())
+    np.testing.assert_allclose(-cw, az, rtol=0, atol=1e-12 * np.abs(az).max())
