@@ -244,8 +244,8 @@ def next_rows_leg(args, case, log, alpha_t, u_t, v_t, w_t, rho_t, rhs_t, p_t):
       around repeated calls.  Each call ends by synchronising its stream, so the time per call
       includes one launch gap; the rates are algorithmic bytes (each array element read or
       written once) over that time, a lower bound on the kernel's own rate.
-    * Multigrid as the solver (red-black SOR V-cycles, no CG; Section 2.1) in float64, to the
-      same tolerance from a zero guess, for SOR factors 1.0 and 1.15."""
+    * Multigrid as the solver (red-black SOR V- and W-cycles, no CG; Section 2.1) in float64, to
+      the same tolerance from a zero guess, for SOR factors 1.0 and 1.15."""
     import torch
     from paper_2104_01636_amd import ppsolve
 
@@ -254,12 +254,17 @@ def next_rows_leg(args, case, log, alpha_t, u_t, v_t, w_t, rho_t, rhs_t, p_t):
     kappa_t = torch.full_like(alpha_t, 2.0 / (0.5 * case.diameter * case.h))  # curvature of a bubble
     out_t = torch.empty_like(alpha_t)
     u2, v2, w2 = u_t.clone(), v_t.clone(), w_t.clone()
+    uc, vc, wc = u_t.clone(), v_t.clone(), w_t.clone()   # cell-centred velocity stand-ins
     calls = {  # name: (launch, algorithmic bytes per cell)
         "density_from_fraction": (lambda: ppsolve.density_from_fraction(alpha_t, 1000.0, 1.2, out=out_t), 16),
         "divergence": (lambda: ppsolve.divergence(u_t, v_t, w_t, case.h, 1.0, out=out_t), 32),
         "project": (lambda: ppsolve.project(rho_t, p_t, u2, v2, w2, case.h, 1e-3), 64),
         "surface_tension_rhs": (lambda: ppsolve.surface_tension_rhs(rho_t, alpha_t, kappa_t, 0.072, case.h,
                                                                     out=out_t), 32),
+        # step 12 on faces and cells with the surface-tension pressure: reads rho, p, pt, three face and
+        # three cell velocity components, writes the six velocity components
+        "correct_velocity": (lambda: ppsolve.correct_velocity(rho_t, p_t, out_t, u2, v2, w2, uc, vc, wc, case.h,
+                                                              1e-3), 120),
     }
     kern = {}
     for name, (call, bpc) in calls.items():
@@ -275,12 +280,13 @@ def next_rows_leg(args, case, log, alpha_t, u_t, v_t, w_t, rho_t, rhs_t, p_t):
         kern[name] = {"us_per_call": round(us, 2), "calls": reps, "bytes_per_cell": bpc, "GB_per_s": round(gbs, 1),
                       "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"next rows: {name} {us:.1f} us, {gbs:.0f} GB/s")
-    del u2, v2, w2, kappa_t, out_t
+    del u2, v2, w2, uc, vc, wc, kappa_t, out_t
 
     mg = {}
-    for omega in (1.0, 1.15):
+    for cycle, omega in (("V", 1.0), ("V", 1.15), ("W", 1.0), ("W", 1.15)):
+        flags = ppsolve.PP_FLAG_MG_SOLVER | (ppsolve.PP_FLAG_W_CYCLE if cycle == "W" else 0)
         with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, tol=args.tol, max_iters=4000,
-                            flags=ppsolve.PP_FLAG_MG_SOLVER, omega=omega) as S:
+                            flags=flags, omega=omega) as S:
             S.set_density(rho_t)
             times = []
             for k in range(2):  # the first solve is a warm-up
@@ -291,10 +297,10 @@ def next_rows_leg(args, case, log, alpha_t, u_t, v_t, w_t, rho_t, rhs_t, p_t):
                 torch.cuda.synchronize()
                 if k:
                     times.append((time.perf_counter() - a) * 1e3)
-            mg[f"omega_{omega:g}"] = {"time_to_tol_ms": round(times[0], 3), "cycles": int(st["iters"]),
+            mg[f"{cycle}_omega_{omega:g}"] = {"time_to_tol_ms": round(times[0], 3), "cycles": int(st["iters"]),
                                       "ms_per_cycle": round(st["solve_ms"] / max(1, st["iters"]), 4),
                                       "rel_residual": float(f"{st['rel_residual']:.3e}")}
-            log(f"next rows: multigrid solver omega {omega:g}: {times[0]:.1f} ms, {st['iters']} cycles, "
+            log(f"next rows: multigrid solver {cycle}-cycle omega {omega:g}: {times[0]:.1f} ms, {st['iters']} cycles, "
                 f"residual {st['rel_residual']:.2e}")
     return {"around_the_solve": kern, "multigrid_solver_fp64": mg}
 

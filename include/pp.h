@@ -71,6 +71,11 @@ typedef struct {
  * (red-black SOR relaxation accelerated by multigrid, Section 2.1).  Float64
  * mode only. */
 #define PP_FLAG_MG_SOLVER 1
+/* flags, with PP_FLAG_MG_SOLVER only: W-cycles instead of V-cycles -- every coarse
+ * level (down to the single-launch small-level cycle) is visited twice per visit
+ * of the level above, the second time on the residual the first left, e += M (f -
+ * K e), and each coarse correction is added once (no over-correction). */
+#define PP_FLAG_W_CYCLE 2
 
 typedef struct {
     int iters;              /* flexible-CG iterations over all passes (multigrid-solver form: cycles) */
@@ -163,6 +168,22 @@ int pp_divergence(int nx, int ny, int nz, double h, double dt, const double* u, 
  * solve).  rho, p, u, v, w: device, N values each. */
 int pp_project(int nx, int ny, int nz, double h, double dt, const double* rho, const double* p, double* u, double* v,
                double* w, void* hip_stream);
+
+/* Step 12 of Section 2.2 in one pass, in place, after the solve:
+ *   face velocities  u_f -= dt * beta_f * (p_R - p_L) / h        (as pp_project;
+ *                    wall entries i = nx-1 of u and j = ny-1 of v set to zero),
+ *   cell velocities  u_c -= dt * (grad p / rho + grad pt / rho)_{f->c},
+ * where the face term beta_f ((p_R - p_L) + (pt_R - pt_L)) / h (beta_f =
+ * 2/(rho_L + rho_R), zero on the walls, each pressure's term rounded on its own
+ * and then added) is averaged to the cell centre from the two faces bounding it
+ * along each axis: (g_west + g_east)/2 for uc, likewise vc and wc (the
+ * face-to-cell counterpart of the linear averaging in the note after the step
+ * list).  pt, the surface-tension pressure of step 6, may be NULL (no
+ * surface-tension term).  u, v, w hold the +x/+y/+z face of every cell; uc, vc,
+ * wc the cell-centred components.  Device arrays of N values; the call returns
+ * after the work on hip_stream (may be NULL) is done. */
+int pp_correct_velocity(int nx, int ny, int nz, double h, double dt, const double* rho, const double* p, const double* pt,
+                        double* u, double* v, double* w, double* uc, double* vc, double* wc, void* hip_stream);
 
 /* Right-hand side of the surface-tension pressure equation (Section 2.1,
  * eq. ppe_surface_tension with the interface force of eq. jump_condition as

@@ -365,6 +365,22 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(int n, T* __restrict__ x, 
     if (want_red) reduce_finish<2>(acc, R);
 }
 
+// r = f - K x on any level from its stored face weights (one thread per cell
+// column): the coarse residual of a W-cycle's second visit.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_residual(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ x,
+                                                    T* __restrict__ r, int kper)
+{
+    const Tile t = tile(L.nx, L.ny, L.nz, kper);
+    if (!t.act) return;
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int c = cell(L.nx, L.ny, t.i, t.j, k);
+        T s, d;
+        nbsum<T>(L, t.i, t.j, k, c, [&](int m, int, int, int) { return x[m]; }, s, d);
+        r[c] = f[c] - (d * x[c] - s);
+    }
+}
+
 // Coarsest level: x = M f with the dense symmetric matrix M (one block).
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restrict__ M, const T* __restrict__ f, T* __restrict__ x)
@@ -698,6 +714,113 @@ __global__ void __launch_bounds__(kBlock) k_project(int nx, int ny, int nz, doub
         }
         rc = rt;
         pc = pt;
+    }
+}
+
+// Step 12 of Section 2.2 on faces and cells in one pass, in place:
+//   faces: u_f -= dt * beta_f (p_R - p_L)/h (wall faces set to zero), as k_project;
+//   cells: u_c -= dt * (g_W + g_E)/2 per axis, g_f = beta_f (p_R - p_L)/h
+//          [+ beta_f (pt_R - pt_L)/h], zero on the walls: the face-to-cell average
+//          of the face pressure terms of p and (with PT) the surface-tension
+//          pressure pt.
+// Each thread walks its z range carrying rho, p, pt of the plane above and the
+// top-face term into the next plane (as that plane's own values and bottom-face
+// term: the same operands in the same order, so the same rounding).  A thread
+// forms its cell's east and north faces; the west face term is the east term of
+// the lane before it and the south term the north term of the row below (LDS,
+// one barrier per plane).  East values come from the lane after it, north values
+// from global memory (the row above is being read by the block).  Threads outside
+// the grid read clamped cells, take part in the exchanges and barriers, and store
+// nothing.
+template <bool PT>
+__global__ void __launch_bounds__(kBlock) k_correct_velocity(int nx, int ny, int nz, double h, double dt,
+                                                            const double* __restrict__ rho, const double* __restrict__ p,
+                                                            const double* __restrict__ pt, double* __restrict__ u,
+                                                            double* __restrict__ v, double* __restrict__ w,
+                                                            double* __restrict__ uc, double* __restrict__ vc,
+                                                            double* __restrict__ wc, int kper)
+{
+#pragma clang fp contract(off)
+    __shared__ double sgn[2][kBlock];  // north-face term of each thread's cell, by plane parity
+    const Tile t = tile(nx, ny, nz, kper);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int sy = nx, sz = nx * ny;
+    const int ic = min(t.i, nx - 1), jc = min(t.j, ny - 1);
+    const bool has_e = ic < nx - 1, has_n = jc < ny - 1, has_w = ic > 0, has_s = jc > 0;
+    // face term of pressure q across the face between cells a (lower) and b (upper)
+    auto term = [&](double beta, double qa, double qb) { return beta * ((qb - qa) / h); };
+    int c = cell(nx, ny, ic, jc, t.k0);
+    double rc = rho[c], pc = p[c], tc = PT ? pt[c] : 0.0;
+    double gb;  // bottom-face term of the current plane
+    {
+        const int cb = t.k0 > 0 ? c - sz : c + (nz - 1) * sz;
+        const double beta = 2.0 / (rho[cb] + rc);
+        gb = term(beta, p[cb], pc);
+        if (PT) gb = gb + term(beta, pt[cb], tc);
+    }
+    int par = 0;
+    for (int k = t.k0; k < t.k1; ++k, c += sz, par ^= 1) {
+        const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
+        const double rt = rho[ct], ptop = p[ct], ttop = PT ? pt[ct] : 0.0;
+        // east neighbour: the lane after this one; the tile's last lane reads it
+        double re = __shfl_down(rc, 1, 64), pe = __shfl_down(pc, 1, 64), te = PT ? __shfl_down(tc, 1, 64) : 0.0;
+        if (threadIdx.x == blockDim.x - 1 && has_e) {
+            re = rho[c + 1];
+            pe = p[c + 1];
+            if (PT) te = pt[c + 1];
+        }
+        const int cn = has_n ? c + sy : c;
+        const double rn = rho[cn], pn = p[cn], tn = PT ? pt[cn] : 0.0;
+        // east, north and top face: the p term (face projection) and the total term
+        double ge_p = 0.0, gn_p = 0.0, ge = 0.0, gn = 0.0;
+        if (has_e) {
+            const double beta = 2.0 / (rc + re);
+            ge_p = term(beta, pc, pe);
+            ge = PT ? ge_p + term(beta, tc, te) : ge_p;
+        }
+        if (has_n) {
+            const double beta = 2.0 / (rc + rn);
+            gn_p = term(beta, pc, pn);
+            gn = PT ? gn_p + term(beta, tc, tn) : gn_p;
+        }
+        const double beta_t = 2.0 / (rc + rt);
+        const double gt_p = term(beta_t, pc, ptop);
+        const double gt = PT ? gt_p + term(beta_t, tc, ttop) : gt_p;
+        // west face: the east term of the lane before; the tile's first lane forms it
+        double gw = __shfl_up(ge, 1, 64);
+        if (threadIdx.x == 0) {
+            gw = 0.0;
+            if (has_w) {
+                const double rw = rho[c - 1], beta = 2.0 / (rw + rc);
+                gw = term(beta, p[c - 1], pc);
+                if (PT) gw = gw + term(beta, pt[c - 1], tc);
+            }
+        }
+        sgn[par][tid] = gn;
+        __syncthreads();
+        double gs;
+        if (threadIdx.y > 0) {
+            gs = sgn[par][tid - blockDim.x];
+        } else {
+            gs = 0.0;
+            if (has_s) {
+                const double rs = rho[c - sy], beta = 2.0 / (rs + rc);
+                gs = term(beta, p[c - sy], pc);
+                if (PT) gs = gs + term(beta, pt[c - sy], tc);
+            }
+        }
+        if (t.act) {
+            u[c] = has_e ? u[c] - dt * ge_p : 0.0;
+            v[c] = has_n ? v[c] - dt * gn_p : 0.0;
+            w[c] = w[c] - dt * gt_p;
+            uc[c] = uc[c] - dt * (0.5 * (gw + ge));
+            vc[c] = vc[c] - dt * (0.5 * (gs + gn));
+            wc[c] = wc[c] - dt * (0.5 * (gb + gt));
+        }
+        gb = gt;
+        rc = rt;
+        pc = ptop;
+        tc = ttop;
     }
 }
 

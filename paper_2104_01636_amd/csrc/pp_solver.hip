@@ -188,6 +188,7 @@ struct Lev {
     T *rhs = nullptr, *c = nullptr, *c2 = nullptr;
     T *xk = nullptr, *d = nullptr, *d2 = nullptr, *q = nullptr;  // Krylov levels
     T *d_a = nullptr, *d_b = nullptr;  // the two search-direction buffers (d, d2 alternate between them)
+    T *w1 = nullptr, *rr = nullptr;    // W-cycle: the first visit's correction, the coarse residual
 };
 
 // Event pair around one timed launch (see TimeScope).
@@ -239,6 +240,7 @@ struct Params {
                                 // latency); between them the overlap costs more than it saves
     double omega = 1.0;         // SOR factor of the red-black smoother
     bool mg_solver = false;     // multigrid cycles as the solver (no Krylov outer iteration)
+    int gamma = 1;              // coarse-grid visits per cycle in that form: 1 V-cycle, 2 W-cycle
     bool march = true;          // plane-marching stencil kernels (else one thread per cell column)
     int mbx = 64;               // widest march tile in x
     int mblocks = 768;          // blocks of a 256-thread march launch (at most; z split to reach it)
@@ -395,7 +397,8 @@ static bool valid_cfg(const pp_config* cfg, std::string* why)
     if (cfg->mode != PP_FP64 && cfg->mode != PP_FP32_REFINED) { if (why) *why = "unknown mode"; return false; }
     if (cfg->omega < 0.0 || cfg->omega >= 2.0 || !std::isfinite(cfg->omega)) { if (why) *why = "omega must be in [0, 2)"; return false; }
     if ((cfg->flags & PP_FLAG_MG_SOLVER) && cfg->mode != PP_FP64) { if (why) *why = "the multigrid-solver form is float64 only"; return false; }
-    if (cfg->flags & ~PP_FLAG_MG_SOLVER) { if (why) *why = "unknown flag bits"; return false; }
+    if ((cfg->flags & PP_FLAG_W_CYCLE) && !(cfg->flags & PP_FLAG_MG_SOLVER)) { if (why) *why = "W-cycles need the multigrid-solver form"; return false; }
+    if (cfg->flags & ~(PP_FLAG_MG_SOLVER | PP_FLAG_W_CYCLE)) { if (why) *why = "unknown flag bits"; return false; }
     // 32-bit cell indices: the largest index plus one plane stride (a z-neighbour
     // read) must fit in an int
     if ((size_t)cfg->nx * cfg->ny * cfg->nz + (size_t)cfg->nx * cfg->ny > (size_t)INT_MAX) {
@@ -501,6 +504,10 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
             if (l > 0) V.rhs = P.template take<T>(V.n);
             V.c = P.template take<T>(V.n);
             if (l < nl - 1) V.c2 = P.template take<T>(V.n);
+            if (prm.gamma == 2 && l >= 1 && l < nl - 1) {
+                V.w1 = P.template take<T>(V.n);
+                V.rr = P.template take<T>(V.n);
+            }
             if (V.kcyc) {
                 V.xk = P.template take<T>(V.n);
                 V.d = V.d_a = P.template take<T>(V.n);
@@ -868,6 +875,8 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
 
 template <class T>
 static T* kcycle(Handle* H, Hier<T>& Hh, int l);
+template <class T>
+static T* second_visit(Handle* H, Hier<T>& Hh, int m, T* e);
 
 // Red-black sweeps of level l before and after its coarse correction.
 template <class T>
@@ -996,8 +1005,30 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     } else {
         e = mgcycle(H, Hh, l + 1, C.rhs, 0, (const T*)nullptr);
         wc = (T)H->prm.wc;
+        if (H->prm.gamma == 2 && C.w1 && l + 1 != Hh.tail) e = second_visit(H, Hh, l + 1, e);
     }
     return cycle_post(H, V, l, nu, f, V.c, e, wc, V.c2, ndot, q);
+}
+
+// W-cycle: the second stationary visit of level m, e <- e + M (f_m - K_m e),
+// with M one cycle from level m (returns the level's w1 buffer).
+template <class T>
+static T* second_visit(Handle* H, Hier<T>& Hh, int m, T* e)
+{
+    Lev<T>& C = Hh.L[m];
+    const Coefs one = coef(H, G_ONE, -1, 1.0);
+    const dim3 lg = lin_grid(C.n);
+    k_update_xr<T><<<lg, kBlock, 0, H->stream>>>((int)C.n, C.w1, e, (T*)nullptr, (const T*)nullptr, one, 1, 1, 0,
+                                                 red(H, G_FN2), (float*)nullptr, 1);
+    check_launch();
+    const Geo g = geo(C.nx, C.ny, C.nz);
+    k_residual<T><<<g.grid, g.block, 0, H->stream>>>(C.v, C.rhs, C.w1, C.rr, g.kper);
+    check_launch();
+    T* e2 = mgcycle(H, Hh, m, C.rr, 0, (const T*)nullptr);
+    k_update_xr<T><<<lg, kBlock, 0, H->stream>>>((int)C.n, C.w1, e2, (T*)nullptr, (const T*)nullptr, one, 0, 1, 0,
+                                                 red(H, G_FN2), (float*)nullptr, 1);
+    check_launch();
+    return C.w1;
 }
 
 template <class T>
@@ -1348,6 +1379,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
         p.kmax = 0;  // plain V-cycles: no Krylov steps anywhere in this form
         p.nuv = 0;   // and post_sweeps (default 2) on every coarse level: as a stationary
                      // iteration the cycle needs them (with one sweep it diverges)
+        if (cfg->flags & PP_FLAG_W_CYCLE) p.gamma = 2;  // two visits of each coarse level
     }
     if (const char* s = getenv("PP_KMAX")) p.kmax = atoi(s);
     if (const char* s = getenv("PP_KMIN")) p.kmin = std::max(0, atoi(s));
@@ -1833,6 +1865,28 @@ int pp_rel_residual_noalloc(int nx, int ny, int nz, double h, const double* rho,
         double* buf = scratch_of_current_device();
         return rel_residual_on((hipStream_t)hip_stream, nx, ny, nz, h, rho, rhs, p, rel_out, buf,
                                buf + (size_t)kMaxPartialBlocks * kMaxRed);
+    });
+}
+
+int pp_correct_velocity(int nx, int ny, int nz, double h, double dt, const double* rho, const double* p, const double* pt,
+                        double* u, double* v, double* w, double* uc, double* vc, double* wc, void* hip_stream)
+{
+    if (!rho || !p || !u || !v || !w || !uc || !vc || !wc) { g_thread_err = "null pointer"; return PP_ERR_INVALID; }
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || !(dt > 0.0) || !grid_fits_int(nx, ny, nz)) {
+        g_thread_err = "bad sizes, h or dt";
+        return PP_ERR_INVALID;
+    }
+    return guarded(nullptr, [&]() -> int {
+        Geo g = geo(nx, ny, nz, 8192);
+        if (pt)
+            k_correct_velocity<true><<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h, dt, rho, p, pt, u, v, w,
+                                                                                      uc, vc, wc, g.kper);
+        else
+            k_correct_velocity<false><<<g.grid, g.block, 0, (hipStream_t)hip_stream>>>(nx, ny, nz, h, dt, rho, p, pt, u, v,
+                                                                                       w, uc, vc, wc, g.kper);
+        check_launch();
+        PP_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+        return PP_OK;
     });
 }
 

@@ -30,7 +30,8 @@ MODES = {"fp64": 0, "fp32_refined": 1}
 # Every entry point declared in include/pp.h.
 EXPORTS = ("pp_footprint_bytes", "pp_create", "pp_set_density", "pp_solve", "pp_apply", "pp_presmooth_restrict",
            "pp_prolong_postsmooth", "pp_destroy",
-           "pp_last_error", "pp_density_from_fraction", "pp_divergence", "pp_project", "pp_surface_tension_rhs",
+           "pp_last_error", "pp_density_from_fraction", "pp_divergence", "pp_project", "pp_correct_velocity",
+           "pp_surface_tension_rhs",
            "pp_rel_residual", "pp_rel_residual_noalloc", "pp_kernel_timing", "pp_version")
 
 
@@ -89,6 +90,8 @@ def lib():
         L.pp_version.restype = ctypes.c_char_p
         L.pp_project.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp, vp]
         L.pp_surface_tension_rhs.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp]
+        L.pp_correct_velocity.argtypes = [ci, ci, ci, cd, cd, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.pp_correct_velocity.restype = ci
         L.pp_rel_residual.argtypes = [ci, ci, ci, cd, vp, vp, vp, ctypes.POINTER(cd), vp]
         L.pp_rel_residual.restype = ci
         L.pp_rel_residual_noalloc.argtypes = [ci, ci, ci, cd, vp, vp, vp, ctypes.POINTER(cd), vp]
@@ -110,6 +113,7 @@ def _check(rc: int, handle=None):
 
 
 PP_FLAG_MG_SOLVER = 1
+PP_FLAG_W_CYCLE = 2
 
 
 def make_config(nx, ny, nz, h=None, mode="fp64", tol=1e-10, max_iters=1000, pre_sweeps=0, post_sweeps=0, flags=0,
@@ -262,6 +266,20 @@ def project(rho: torch.Tensor, p: torch.Tensor, u: torch.Tensor, v: torch.Tensor
     _check(lib().pp_project(nx, ny, nz, float(h), float(dt), _dev(rho, n, "rho"), _dev(p, n, "p"), _dev(u, n, "u"),
                             _dev(v, n, "v"), _dev(w, n, "w"), _stream_ptr(stream)))
     return u, v, w
+
+
+def correct_velocity(rho: torch.Tensor, p: torch.Tensor, pt: torch.Tensor | None, u: torch.Tensor, v: torch.Tensor,
+                     w: torch.Tensor, uc: torch.Tensor, vc: torch.Tensor, wc: torch.Tensor, h: float, dt: float = 1.0,
+                     stream=None):
+    """Step 12 in place: face velocities projected with p, cell velocities corrected with
+    (grad p / rho + grad pt / rho) averaged from faces to cells (pt may be None)."""
+    nz, ny, nx = u.shape
+    n = u.numel()
+    _check(lib().pp_correct_velocity(nx, ny, nz, float(h), float(dt), _dev(rho, n, "rho"), _dev(p, n, "p"),
+                                     _dev(pt, n, "pt") if pt is not None else None, _dev(u, n, "u"), _dev(v, n, "v"),
+                                     _dev(w, n, "w"), _dev(uc, n, "uc"), _dev(vc, n, "vc"), _dev(wc, n, "wc"),
+                                     _stream_ptr(stream)))
+    return u, v, w, uc, vc, wc
 
 
 def surface_tension_rhs(rho: torch.Tensor, alpha: torch.Tensor, kappa: torch.Tensor, sigma: float, h: float, out=None,

@@ -109,3 +109,54 @@ def test_projection_and_surface_rhs_bitexact_multi_plane(shape):
     np.testing.assert_array_equal(c(u_t), un)
     np.testing.assert_array_equal(c(v_t), vn)
     np.testing.assert_array_equal(c(w_t), wn)
+
+
+SHAPES = [(2, 2, 2), (3, 5, 4), (7, 6, 8), (16, 8, 8), (33, 17, 10), (64, 32, 32), (512, 256, 256)]  # (nz, ny, nx)
+
+
+@pytest.mark.parametrize("with_pt", [False, True], ids=["p_only", "p_and_pt"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_correct_velocity_bit_exact(shape, with_pt):
+    """Step 12 on faces and cells in one pass (pp_correct_velocity) against the
+    oracle's face projection and cell correction, bit for bit, with and without
+    the surface-tension pressure; ragged tiles and the full 256x256x512 grid."""
+    nz, ny, nx = shape
+    print("correct_velocity", shape, with_pt, flush=True)
+    case = W.preset("duct256") if nx == 256 else W.random_small_case(70 + sum(shape), nx, ny, nz)
+    rng = np.random.default_rng(sum(shape))
+    rho = P.density_from_fraction(case.alpha)
+    p = rng.standard_normal(shape)
+    pt = rng.standard_normal(shape) * 0.1 if with_pt else None
+    uc, vc, wc = (rng.standard_normal(shape) for _ in range(3))
+    dt = 0.37
+    un, vn, wn = P.project(rho, p, case.u, case.v, case.w, case.h, dt)
+    ucn, vcn, wcn = P.correct_cell_velocity(rho, p, pt, uc, vc, wc, case.h, dt)
+    ts = [g(a) for a in (case.u, case.v, case.w, uc, vc, wc)]
+    ppsolve.correct_velocity(g(rho), g(p), g(pt) if with_pt else None, *ts, case.h, dt)
+    for got, want in zip(ts, (un, vn, wn, ucn, vcn, wcn)):
+        np.testing.assert_array_equal(c(got), want)
+
+
+def test_correct_velocity_after_solve_removes_divergence_and_matches_average():
+    """After the step-11 solve the corrected face velocities are divergence-free to
+    the solve's residual, and the cell correction equals the face correction
+    averaged to the cells."""
+    case = W.preset("duct32")
+    dt = 0.5
+    rho_t = ppsolve.density_from_fraction(g(case.alpha))
+    u_t, v_t, w_t = g(case.u), g(case.v), g(case.w)
+    b_t = ppsolve.divergence(u_t, v_t, w_t, case.h, dt)
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, tol=1e-12) as S:
+        S.set_density(rho_t)
+        p_t, _ = S.solve(b_t)
+    zero = [torch.zeros_like(u_t) for _ in range(3)]
+    ppsolve.correct_velocity(rho_t, p_t, None, u_t, v_t, w_t, *zero, case.h, dt)
+    d_new = c(ppsolve.divergence(u_t, v_t, w_t, case.h))
+    b = P.divergence(case.u, case.v, case.w, case.h, dt)
+    assert np.max(np.abs(d_new - d_new.mean())) < 1e-9 * np.max(np.abs(b))
+    du, dv, dw = case.u - c(u_t), case.v - c(v_t), case.w - c(w_t)
+    du[:, :, -1] = 0.0
+    dv[:, -1, :] = 0.0
+    ax, ay, az = P.face_to_cell(du, dv, dw)
+    for got, want in zip(zero, (ax, ay, az)):
+        np.testing.assert_allclose(-c(got), want, rtol=0, atol=1e-12 * np.abs(want).max())
