@@ -1,0 +1,229 @@
+// pp_rowwave.hpp -- row-wave plane-marching kernels for the finest level (gfx950).
+//
+// The same operations as the march kernels of pp_march.hpp, laid out so that a
+// wavefront covers one whole grid row: the level's x extent is 64 * CPT cells
+// and lane l owns the CPT consecutive cells 64-aligned at l * CPT.  A block of
+// 64 x BY threads is BY rows (one per wavefront) and walks a range of z planes.
+//   * x neighbours are in the lane's own registers or in the next / previous
+//     lane (wavefront shuffles); the walls at i = 0 and i = nx-1 bound every
+//     row, so there is no x halo at all (on a tiled row every tile edge would
+//     fetch a whole cache line for one element per array and plane);
+//   * y neighbours of the block's inner rows come from a double-buffered LDS
+//     copy of the plane (one barrier per plane); the first and last row of the
+//     block (whole wavefronts, so the branch is uniform) also load the row
+//     beyond the tile, one full row per array;
+//   * z neighbours come from a three-plane register queue, as in pp_march.hpp;
+//   * each lane loads CPT consecutive elements per array and plane, which the
+//     compiler issues as wide loads, and the loads of plane k+1 are in flight
+//     while plane k is computed: several times the bytes in flight per wave of a
+//     one-cell-per-lane march, which is what a bandwidth-bound pass needs.
+// Face weights are formed from the density (finest level): beta_f = 2/(rho_L +
+// rho_R), float64 by IEEE division (bit-equal to the set-up), float32 by the
+// hardware reciprocal; a cell's west weight is its west neighbour's east weight
+// and its bottom weight the top weight of the plane below, so a cell divides
+// for its east, north, south and top faces only.
+#pragma once
+#include "pp_march.hpp"
+
+namespace pp {
+
+// Shuffles of a value one lane down (lane l gets lane l+1's value) and up.
+template <class T>
+__device__ inline T lane_next(T v) { return __shfl_down(v, 1, 64); }
+template <class T>
+__device__ inline T lane_prev(T v) { return __shfl_up(v, 1, 64); }
+
+// Tile (row band and z range) of this block: grid.y bands of SY rows, grid.z
+// z ranges, blocks dealt to the XCDs in contiguous runs (see tile_of_block).
+__device__ inline void rw_tile(int& by, int& bz, int xcd)
+{
+    int bx;
+    tile_of_block(bx, by, bz, xcd);
+}
+
+// One plane's global inputs of a row-wave lane: own raw inputs at k+1 (the
+// plane above, for the z queue), apply's extras, the density at k+1, and for
+// the first / last wavefront of the block the raw inputs and density of the
+// row beyond the tile.
+template <class T, int CPT, class Raw, class Ex>
+struct RwRegs {
+    Raw rn[CPT];   // raw inputs at (i, j, k+1)
+    Ex ex[CPT];    // apply's extras at (i, j, k)
+    T rho_n[CPT];  // density at (i, j, k+1)
+    Raw rh[CPT];   // halo row raw inputs at (i, j +- 1, k)
+    T rho_h[CPT];  // halo row density at (i, j +- 1, k)
+};
+
+// The row-wave march.  Op is the same interface as for march() (pp_march.hpp):
+// load / val / extra / apply per cell; every lane calls apply for each of its
+// cells at every plane (act false outside the grid).
+template <class T, int CPT, int BY, class Op, class Acc>
+__device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op, Acc& acc)
+{
+    using Raw = typename Op::Raw;
+    using Ex = typename Op::Ex;
+    using Regs = RwRegs<T, CPT, Raw, Ex>;
+    constexpr int NX = 64 * CPT;
+    __shared__ T sv[2][BY][NX];   // stencil value of each cell, by plane parity
+    __shared__ T sr[2][BY][NX];   // density of each cell, by plane parity
+    const int lane = threadIdx.x, ty = threadIdx.y;
+    int by, bz;
+    rw_tile(by, bz, xcd);
+    const int j = by * BY + ty;
+    const int k0 = bz * kper, k1 = min(L.nz, k0 + kper);
+    const bool act = j < L.ny;
+    const int jc = min(j, L.ny - 1);
+    const int i0 = lane * CPT;
+    const int sz = L.nx * L.ny;
+    const int cbase = cell(L.nx, L.ny, i0, jc, 0);
+    // the first and last wavefront of the block read the row beyond the tile
+    const bool lo = ty == 0 && jc > 0, hi = ty == BY - 1 && jc < L.ny - 1;
+    const int oj = lo ? -L.nx : (hi ? L.nx : 0);
+    const bool in_n = j < L.ny - 1, in_s = j > 0;
+
+    auto fetch = [&](Regs& S, int k) {
+        const int c = cbase + k * sz;
+        const int kt = k < L.nz - 1 ? k + 1 : 0;
+        const int ct = c + (kt - k) * sz;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            S.rn[e] = op.load(ct + e, i0 + e, jc, kt);
+            S.rho_n[e] = L.rho[ct + e];
+            S.ex[e] = op.extra(c + e);
+        }
+        if (lo || hi) {
+#pragma unroll
+            for (int e = 0; e < CPT; ++e) {
+                S.rh[e] = op.load(c + oj + e, i0 + e, jc + (lo ? -1 : 1), k);
+                S.rho_h[e] = L.rho[c + oj + e];
+            }
+        }
+    };
+
+    // prologue: values at the plane below the first and at the first
+    const int kb0 = k0 > 0 ? k0 - 1 : L.nz - 1;
+    T vm[CPT], vc[CPT], rho_c[CPT], wb[CPT];
+    Raw rc[CPT];
+    {
+        const int c = cbase + k0 * sz, cb = cbase + kb0 * sz;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            vm[e] = act ? op.val(op.load(cb + e, i0 + e, jc, kb0)) : T(0);
+            rc[e] = op.load(c + e, i0 + e, jc, k0);
+            vc[e] = act ? op.val(rc[e]) : T(0);
+            rho_c[e] = L.rho[c + e];
+            wb[e] = face_beta(L.rho[cb + e], rho_c[e]);
+        }
+    }
+    Regs R[2];
+    fetch(R[0], k0);
+
+    auto step = [&](Regs& S, Regs& N, int k, int buf) {
+        const int c = cbase + k * sz;
+        if (k + 1 < k1) fetch(N, k + 1);
+        T vp[CPT];
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            vp[e] = act ? op.val(S.rn[e]) : T(0);
+            sv[buf][ty][i0 + e] = vc[e];
+            sr[buf][ty][i0 + e] = act ? rho_c[e] : T(1);
+        }
+        T vh[CPT];
+        if (lo || hi) {
+#pragma unroll
+            for (int e = 0; e < CPT; ++e) vh[e] = op.val(S.rh[e]);
+        }
+        lds_barrier();
+        // x neighbours: own registers, the previous lane's last cell, the next lane's first
+        const T v_prev = lane_prev(vc[CPT - 1]), v_next = lane_next(vc[0]);
+        const T r_next = lane_next(rho_c[0]);
+        T we[CPT];
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const T re = e < CPT - 1 ? rho_c[e + 1] : r_next;
+            we[e] = (i0 + e < NX - 1) ? face_beta(rho_c[e], re) : T(0);
+        }
+        const T we_prev = lane_prev(we[CPT - 1]);
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int i = i0 + e;
+            const T vw = e > 0 ? vc[e - 1] : v_prev;
+            const T ve = e < CPT - 1 ? vc[e + 1] : v_next;
+            const T ww = e > 0 ? we[e - 1] : (i > 0 ? we_prev : T(0));
+            T vs, vn, rs, rn;
+            if (ty > 0) { vs = sv[buf][ty - 1][i]; rs = sr[buf][ty - 1][i]; }
+            else { vs = lo ? vh[e] : T(0); rs = lo ? S.rho_h[e] : T(1); }
+            if (ty < BY - 1) { vn = sv[buf][ty + 1][i]; rn = sr[buf][ty + 1][i]; }
+            else { vn = hi ? vh[e] : T(0); rn = hi ? S.rho_h[e] : T(1); }
+            const T ws = in_s ? face_beta(rs, rho_c[e]) : T(0);
+            const T wn = in_n ? face_beta(rho_c[e], rn) : T(0);
+            const T wt = face_beta(rho_c[e], S.rho_n[e]);
+            Stencil<T> st;
+            st.s = ww * vw + we[e] * ve + ws * vs + wn * vn + wb[e] * vm[e] + wt * vp[e];
+            st.d = ww + we[e] + ws + wn + wb[e] + wt;
+            st.ww = ww;
+            st.we = we[e];
+            st.ws = ws;
+            st.wn = wn;
+            st.wb = wb[e];
+            st.wt = wt;
+            op.apply(c + e, i, j, k, vc[e], rc[e], S.ex[e], st, acc, act);
+            wb[e] = wt;
+        }
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            vm[e] = vc[e];
+            vc[e] = vp[e];
+            rc[e] = S.rn[e];
+            rho_c[e] = S.rho_n[e];
+        }
+    };
+
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+        step(R[0], R[1], k, (k - k0) & 1);
+        step(R[1], R[0], k + 1, (k + 1 - k0) & 1);
+    }
+    if (k < k1) step(R[0], R[1], k, (k - k0) & 1);
+}
+
+// Rows (wavefronts) of a row-wave block: 4 or 8.
+constexpr int kRwRowsMax = 8;
+
+// Row-wave variants of the finest-level float64 passes of the Krylov step
+// (same operations and reductions as m_dir_apply, m_true_residual, m_apply).
+template <int CPT, int BY, class TZ, bool BETA, bool FINE>
+__global__ void __launch_bounds__(64 * BY) r_dir_apply(LevelView<double> L, const TZ* __restrict__ z,
+                                                      const double* __restrict__ dold, double* __restrict__ dnew,
+                                                      double* __restrict__ q, const double* __restrict__ r,
+                                                      double* __restrict__ x, Coefs beta, Coefs mean, int use_mean,
+                                                      Coefs aprev, int kper, int xcd, Reduce R)
+{
+    OpDir<double, TZ, BETA, FINE> op{z, dold, r, dnew, q, x, BETA ? beta.get() : 0.0, use_mean ? mean.get() : 0.0,
+                                     (FINE && BETA) ? aprev.get() : 0.0};
+    double acc[2] = {0.0, 0.0};
+    march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
+    reduce_finish<2>(acc, R);
+}
+
+template <int CPT, int BY>
+__global__ void __launch_bounds__(64 * BY) r_true_residual(LevelView<double> L, const double* __restrict__ f,
+                                                          const double* __restrict__ x, double* __restrict__ r, int kper,
+                                                          int xcd, Reduce R)
+{
+    OpResidual<double> op{f, x, r};
+    double acc[2] = {0.0, 0.0};
+    march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
+    reduce_finish<2>(acc, R);
+}
+
+template <int CPT, int BY>
+__global__ void __launch_bounds__(64 * BY) r_apply(LevelView<double> L, const double* __restrict__ x, double* __restrict__ y,
+                                                  double inv_h2, int kper, int xcd)
+{
+    OpApply<double> op{x, y, inv_h2};
+    double acc[1] = {0.0};
+    march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
+}
+
+}  // namespace pp

@@ -32,6 +32,8 @@
 #include "pp_kernels.hpp"
 #include "pp_march.hpp"
 #include "pp_tail.hpp"
+#include "pp_rowwave.hpp"
+#include "pp_rowfused.hpp"
 #include "../../include/pp.h"
 
 #include <algorithm>
@@ -249,6 +251,16 @@ struct Params {
     int oxcd = 1;               // the same for the overlapped-tile launches (-1: as xcd); their
                                 // ring rows then come from the L2 of the XCD, measured 3 % faster
     bool rho = true;            // finest-level march kernels form the weights from the density
+    bool rw = true;             // row-wave kernels (a wavefront per whole row) for the finest-level float64
+                                // residual and operator when nx is 64, 128, 192 or 256
+    bool rwdir = false;         // ... and for the direction update (measured slower: 435 against 414 us)
+    int rwblocks = 512;         // blocks of a row-wave launch, at most (z split to reach it)
+    int rwrows = 8;             // rows (wavefronts) of a row-wave block: 4 or 8
+    bool rwf = true;            // row-wave forms of the fused float32 finest-level passes (nx 128 or 256)
+    int rwfrows = 8;            // their rows per block, ring included: 8 or 16
+    int rwfblocks = 512;        // their blocks per launch, at most
+    int rwxcd = 1;              // XCD-aware band order for the row-wave launches (neighbouring row bands,
+                                // whose halo rows overlap, share an L2)
 };
 
 struct Handle {
@@ -712,6 +724,46 @@ static MGeo march_geo(const Handle* H, const LevelView<T>& v, int bx_max, bool e
     return mgeo(v.nx, v.ny, v.nz, bx_max, even_k, H->prm.mblocks, kBlock);
 }
 
+// Row-wave geometry of a finest-level float64 pass (cpt = cells per lane), or
+// cpt = 0 when the row-wave kernels do not apply: they need the density-formed
+// weights and a row of 64, 128, 192 or 256 cells.
+struct RwGeo {
+    dim3 grid, block;
+    int kper = 0, cpt = 0, rows = 8;
+};
+static RwGeo rw_geo(const Handle* H, const LevelView<double>& v)
+{
+    RwGeo g;
+    if (!H->prm.rw || !H->prm.march || !v.rho || v.nx % 64 != 0 || v.nx > 256) return g;
+    const int rows = H->prm.rwrows;
+    const int gy = (v.ny + rows - 1) / rows;
+    int gz = std::max(1, std::min(v.nz, H->prm.rwblocks / gy));
+    const int kper = (v.nz + gz - 1) / gz;
+    gz = (v.nz + kper - 1) / kper;
+    if ((size_t)gy * gz > (size_t)kMaxPartialBlocks) return g;
+    g.grid = dim3(1, gy, gz);
+    g.block = dim3(64, rows, 1);
+    g.rows = rows;
+    g.kper = kper;
+    g.cpt = v.nx / 64;
+    return g;
+}
+// Calls f(BxC<cpt>{}, BxC<rows>{}) for the row-wave instantiations.
+template <class F>
+static void with_cpt(const RwGeo& g, F&& f)
+{
+    auto rows = [&](auto C) {
+        if (g.rows == 4) f(C, BxC<4>{});
+        else f(C, BxC<8>{});
+    };
+    switch (g.cpt) {
+    case 1: rows(BxC<1>{}); break;
+    case 2: rows(BxC<2>{}); break;
+    case 3: rows(BxC<3>{}); break;
+    default: rows(BxC<4>{}); break;
+    }
+}
+
 // Launchers: the plane-march kernels, or the per-column kernels when the march is off.
 
 template <class T>
@@ -774,11 +826,54 @@ static void launch_restrict(Handle* H, const LevelView<T>& v, const T* f, const 
     check_launch();
 }
 
+// Row-wave geometry of a fused float32 finest-level pass: bands of rows - 2
+// own rows (plus a ring row on each side), z ranges of an even number of
+// planes; cpt = 0 when it does not apply (density-formed weights, nx 128 or 256).
+static RwGeo rwf_geo(const Handle* H, const LevelView<float>& v, int max_blocks)
+{
+    RwGeo g;
+    if (!H->prm.rwf || !H->prm.march || !v.rho || (v.nx != 128 && v.nx != 256)) return g;
+    const int rows = H->prm.rwfrows, sy = rows - 2;
+    const int gy = (v.ny + sy - 1) / sy;
+    int gz = std::max(1, std::min(v.nz / 2, max_blocks / gy));
+    int kper = (v.nz + gz - 1) / gz;
+    if (kper & 1) ++kper;
+    gz = (v.nz + kper - 1) / kper;
+    if ((size_t)gy * gz > (size_t)kMaxPartialBlocks) return g;
+    g.grid = dim3(1, gy, gz);
+    g.block = dim3(64, rows, 1);
+    g.kper = kper;
+    g.cpt = v.nx / 64;
+    g.rows = rows;
+    return g;
+}
+template <class F>
+static void with_cpt_even(const RwGeo& g, F&& f)
+{
+    auto rows = [&](auto C) {
+        if (g.rows == 16) f(C, BxC<16>{});
+        else f(C, BxC<8>{});
+    };
+    if (g.cpt == 2) rows(BxC<2>{});
+    else rows(BxC<4>{});
+}
+
 // First sweep from zero and restriction of its residual in one launch (a
 // level smoothed once before the coarse correction).
 template <class T>
 static void launch_first_restrict(Handle* H, const LevelView<T>& v, const T* f, T* x, T* rc)
 {
+    if constexpr (std::is_same_v<T, float>) {
+        const RwGeo rg = rwf_geo(H, v, H->prm.rwfblocks);
+        if (rg.cpt) {
+            with_cpt_even(rg, [&](auto C, auto Y) {
+                r_first_restrict<decltype(C)::value, decltype(Y)::value>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, rc, rg.kper, H->prm.rwxcd, (T)H->prm.omega);
+            });
+            check_launch();
+            return;
+        }
+    }
     const MGeo g = ovl_geo(v.nx, v.ny, v.nz, H->prm.oblocks);
     const int xcd = H->prm.oxcd < 0 ? xcd_of(H, v) : H->prm.oxcd;
     with_rho(v, [&](auto R) {
@@ -794,6 +889,17 @@ template <class T, int NDOT, class TQ>
 static dim3 launch_prolong_half(Handle* H, const LevelView<T>& v, const T* f, const T* x, const T* e, T wc, T* z,
                                 const TQ* q, const Reduce& R)
 {
+    if constexpr (std::is_same_v<T, float>) {
+        const RwGeo rg = rwf_geo(H, v, H->prm.rwfblocks);
+        if (rg.cpt) {
+            with_cpt_even(rg, [&](auto C, auto Y) {
+                r_prolong_half<decltype(C)::value, decltype(Y)::value, NDOT, TQ><<<rg.grid, rg.block, 0, H->stream>>>(
+                    v, f, x, e, wc, z, q, R, rg.kper, H->prm.rwxcd, (T)H->prm.omega);
+            });
+            check_launch();
+            return rg.grid;
+        }
+    }
     // a reducing launch writes one partial per block: at most kMaxPartialBlocks blocks
     const MGeo g = ovl_geo(v.nx, v.ny, v.nz, NDOT > 0 ? std::min(H->prm.oblocks, kMaxPartialBlocks) : H->prm.oblocks);
     if (NDOT > 0 && (size_t)g.grid.x * g.grid.y * g.grid.z > (size_t)kMaxPartialBlocks)
@@ -831,6 +937,22 @@ template <class T, class TZ, bool FINE = false>
 static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* dold, T* dnew, T* q, const T* r, T* x,
                        Coefs beta, int use_beta, Coefs mean, int use_mean, Coefs aprev, const Reduce& R)
 {
+    if constexpr (FINE && std::is_same_v<T, double>) {
+        const RwGeo rg = H->prm.rwdir ? rw_geo(H, v) : RwGeo{};
+        if (rg.cpt) {
+            with_cpt(rg, [&](auto C, auto Y) {
+                constexpr int CPT = decltype(C)::value, BY = decltype(Y)::value;
+                if (use_beta)
+                    r_dir_apply<CPT, BY, TZ, true, FINE><<<rg.grid, rg.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, rg.kper, H->prm.rwxcd, R);
+                else
+                    r_dir_apply<CPT, BY, TZ, false, FINE><<<rg.grid, rg.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, rg.kper, H->prm.rwxcd, R);
+            });
+            check_launch();
+            return rg.grid;
+        }
+    }
     if (H->prm.march) {
         const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
@@ -1270,11 +1392,19 @@ static double true_residual(Handle* H, const double* x)
 {
     const pp_config& cfg = H->cfg;
     const LevelView<double> v = fine64(H);
+    dim3 grid;
     {
         // reads f, x and the float64 weights (or density); writes r
         TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * (24.0 + 8.0 * weight_arrays(H, v)));
         const Reduce R = red(H, G_TRR, G_TRSUM);
-        if (H->prm.march) {
+        const RwGeo rg = rw_geo(H, v);
+        if (rg.cpt) {
+            with_cpt(rg, [&](auto C, auto Y) {
+                r_true_residual<decltype(C)::value, decltype(Y)::value>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, H->f64, x, H->r64, rg.kper, H->prm.rwxcd, R);
+            });
+            grid = rg.grid;
+        } else if (H->prm.march) {
             const MGeo g = march_geo(H, v, H->prm.mbx);
             with_bx(g.bx, [&](auto B) {
                 with_rho(v, [&](auto W) {
@@ -1282,17 +1412,15 @@ static double true_residual(Handle* H, const double* x)
                         <<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, xcd_of(H, v), R);
                 });
             });
+            grid = g.grid;
         } else {
             const Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
             k_true_residual<<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, R);
+            grid = g.grid;
         }
         check_launch();
     }
-    {
-        const dim3 grid = H->prm.march ? march_geo(H, v, H->prm.mbx).grid
-                                       : geo(cfg.nx, cfg.ny, cfg.nz).grid;
-        finish(H, red(H, G_TRR, G_TRSUM), grid, 2);
-    }
+    finish(H, red(H, G_TRR, G_TRSUM), grid, 2);
     read_slots(H, G_TRR, 2);
     return std::sqrt(std::max(0.0, H->host_slots[G_TRR]));
 }
@@ -1409,6 +1537,14 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_RHO")) p.rho = atoi(s) != 0;
     if (const char* s = getenv("PP_FBLOCKS")) p.fblocks = std::max(32, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBLOCKS")) p.mblocks = std::max(64, std::min(kMaxRedBlocks, atoi(s)));
+    if (const char* s = getenv("PP_RW")) p.rw = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWDIR")) p.rwdir = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWBLOCKS")) p.rwblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
+    if (const char* s = getenv("PP_RWXCD")) p.rwxcd = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWROWS")) p.rwrows = atoi(s) <= 4 ? 4 : 8;
+    if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWFROWS")) p.rwfrows = atoi(s) >= 16 ? 16 : 8;
+    if (const char* s = getenv("PP_RWFBLOCKS")) p.rwfblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBX")) {
         const int b = atoi(s);
         p.mbx = (b >= 64) ? 64 : (b >= 32) ? 32 : (b >= 16) ? 16 : 8;
@@ -1653,8 +1789,15 @@ int pp_apply(pp_handle h, const double* x, double* y)
         PP_HIP(hipSetDevice(H->device));
         enter(H);
         const double inv_h2 = 1.0 / (H->cfg.h * H->cfg.h);
-        if (H->prm.march) {
+        const RwGeo rg = rw_geo(H, fine64(H));
+        if (rg.cpt) {
             // the finest-level operator exactly as the solve's passes form it
+            const LevelView<double> v = fine64(H);
+            with_cpt(rg, [&](auto C, auto Y) {
+                r_apply<decltype(C)::value, decltype(Y)::value>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, x, y, inv_h2, rg.kper, H->prm.rwxcd);
+            });
+        } else if (H->prm.march) {
             const LevelView<double> v = fine64(H);
             const MGeo g = march_geo(H, v, H->prm.mbx);
             with_bx(g.bx, [&](auto B) {

@@ -44,7 +44,8 @@ def inputs(case):
 
 
 SHAPES = [(2, 2, 2), (3, 5, 4), (7, 6, 8), (16, 8, 8), (33, 17, 10), (64, 32, 32)]  # (nz, ny, nx)
-EVEN = [(2, 2, 2), (4, 5, 3), (6, 6, 8), (16, 8, 8), (34, 17, 10), (64, 32, 32)]    # solver grids: nz even
+EVEN = [(2, 2, 2), (4, 5, 3), (6, 6, 8), (16, 8, 8), (34, 17, 10), (64, 32, 32),   # solver grids: nz even;
+        (6, 10, 192), (4, 9, 128), (2, 3, 64)]   # rows of 64-256 cells: the row-wave operator, ragged bands
 
 
 @pytest.mark.parametrize("shape", SHAPES)
