@@ -69,6 +69,8 @@ struct Reduce {
     double* partials;    // [kMaxPartialBlocks * kMaxRed]
     double* out;         // scalar slots receiving the totals
     int slot[kMaxRed];   // slot index per reduced value
+    double* host = nullptr;  // device view of mapped pinned host slots that also receive the totals
+                             // (totals the host reads: no copy launch after the reduction), or null
 };
 
 // Scalars a kernel reads from the device slot array (no host round trip).
@@ -152,6 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_finish(Reduce R, int nblk, in
             double tot = 0.0;
             for (int w = 0; w < kBlock / 64; ++w) tot += sh[w];
             R.out[R.slot[m]] = tot;
+            if (R.host) R.host[R.slot[m]] = tot;
         }
         __syncthreads();
     }

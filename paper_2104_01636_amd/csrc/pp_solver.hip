@@ -305,7 +305,8 @@ struct Handle {
     // reductions
     double* partials = nullptr;
     double* slots = nullptr;
-    double* host_slots = nullptr;  // pinned
+    double* host_slots = nullptr;  // pinned, mapped
+    double* host_slots_dev = nullptr;  // its device view (null: totals are copied back instead)
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double setup_ms = 0.0;
@@ -615,6 +616,14 @@ static Reduce red(Handle* H, int s0, int s1 = 0, int s2 = 0, int s3 = 0)
     R.slot[0] = s0; R.slot[1] = s1; R.slot[2] = s2; R.slot[3] = s3;
     return R;
 }
+// The same for totals the host reads next: the finishing kernel also writes
+// them into the mapped host slots (see fetch_slots).
+static Reduce red_host(Handle* H, int s0, int s1 = 0)
+{
+    Reduce R = red(H, s0, s1);
+    R.host = H->host_slots_dev;
+    return R;
+}
 
 static Coefs coef(Handle* H, int num, int den, double sign) { return Coefs{H->slots, num, den, sign}; }
 
@@ -648,6 +657,15 @@ static void read_slots(Handle* H, int first, int count)
 {
     PP_HIP(hipMemcpyAsync(H->host_slots + first, H->slots + first, sizeof(double) * count, hipMemcpyDeviceToHost, H->stream));
     PP_HIP(hipStreamSynchronize(H->stream));
+}
+
+// Makes host_slots[first, first + count) current after a reduction made with
+// red_host: waits for the stream (the finishing kernel wrote them into the
+// mapped host slots), or copies them back when the slots are not mapped.
+static void fetch_slots(Handle* H, int first, int count)
+{
+    if (H->host_slots_dev) PP_HIP(hipStreamSynchronize(H->stream));
+    else read_slots(H, first, count);
 }
 
 static void write_slots(Handle* H, int first, const double* v, int count)
@@ -1227,7 +1245,7 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
         finish(H, R, grid, 2);
     }
     {
-        const Reduce R = red(H, lslot(0, S_RR), lslot(0, S_RSUM));
+        const Reduce R = red_host(H, lslot(0, S_RR), lslot(0, S_RSUM));
         {
             // reads r and q; writes r and the float32 copy of r
             TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (24.0 + (H->r32 ? 4.0 : 0.0)));
@@ -1299,7 +1317,7 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
         } else {
             krylov_step(H, Hh, k);
         }
-        read_slots(H, lslot(0, S_RR), 1);
+        fetch_slots(H, lslot(0, S_RR), 1);
         rn = std::sqrt(std::max(0.0, H->host_slots[lslot(0, S_RR)]));
         if (!(rn == rn)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
         if (rn <= rnorm_stop) { ++k; break; }
@@ -1327,8 +1345,8 @@ static void set_density(Handle* H, const double* rho)
     // validate: finite and > 0
     k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, 1, red(H, G_RHOSUM, G_RHOBAD));
     check_launch();
-    finish(H, red(H, G_RHOSUM, G_RHOBAD), lin_grid(n0), 2);
-    read_slots(H, G_RHOSUM, 2);
+    finish(H, red_host(H, G_RHOSUM, G_RHOBAD), lin_grid(n0), 2);
+    fetch_slots(H, G_RHOSUM, 2);
     if (H->host_slots[G_RHOBAD] != 0.0)
         throw Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
                                          " entries that are not finite or not > 0");
@@ -1375,15 +1393,15 @@ static double prepare_rhs(Handle* H, const double* rhs)
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, 0, red(H, G_BSUM, G_BBAD));
     check_launch();
-    finish(H, red(H, G_BSUM, G_BBAD), lin_grid(n0), 2);
-    read_slots(H, G_BSUM, 2);
+    finish(H, red_host(H, G_BSUM, G_BBAD), lin_grid(n0), 2);
+    fetch_slots(H, G_BSUM, 2);
     if (H->host_slots[G_BBAD] != 0.0)
         throw Fail(PP_ERR_NONFINITE, "rhs has " + std::to_string((long long)H->host_slots[G_BBAD]) + " non-finite entries");
     k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, H->f64, -cfg.h * cfg.h, coef(H, G_BSUM, -1, 1.0 / (double)n0),
                                                           1, red(H, G_FN2));
     check_launch();
-    finish(H, red(H, G_FN2), lin_grid(n0), 1);
-    read_slots(H, G_FN2, 1);
+    finish(H, red_host(H, G_FN2), lin_grid(n0), 1);
+    fetch_slots(H, G_FN2, 1);
     return std::sqrt(H->host_slots[G_FN2]);
 }
 
@@ -1420,8 +1438,8 @@ static double true_residual(Handle* H, const double* x)
         }
         check_launch();
     }
-    finish(H, red(H, G_TRR, G_TRSUM), grid, 2);
-    read_slots(H, G_TRR, 2);
+    finish(H, red_host(H, G_TRR, G_TRSUM), grid, 2);
+    fetch_slots(H, G_TRR, 2);
     return std::sqrt(std::max(0.0, H->host_slots[G_TRR]));
 }
 
@@ -1718,7 +1736,17 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
         PP_HIP(hipStreamCreateWithFlags(&H->stream, hipStreamNonBlocking));
         PP_HIP(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
         PP_HIP(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
-        PP_HIP(hipHostMalloc((void**)&H->host_slots, sizeof(double) * kSlots, hipHostMallocDefault));
+        PP_HIP(hipHostMalloc((void**)&H->host_slots, sizeof(double) * kSlots, hipHostMallocMapped | hipHostMallocCoherent));
+        {
+            // device view of the host slots: reductions the host reads write their totals there
+            void* dv = nullptr;
+            if (getenv("PP_HOSTSLOTS") && atoi(getenv("PP_HOSTSLOTS")) == 0) dv = nullptr;
+            else if (hipHostGetDevicePointer(&dv, H->host_slots, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                dv = nullptr;
+            }
+            H->host_slots_dev = static_cast<double*>(dv);
+        }
         PP_HIP(hipEventCreate(&H->ev0));
         PP_HIP(hipEventCreate(&H->ev1));
         PP_HIP(hipMemsetAsync(H->slots, 0, kSlots * sizeof(double), H->stream));
