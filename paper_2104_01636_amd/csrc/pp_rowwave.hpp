@@ -42,30 +42,38 @@ __device__ inline void rw_tile(int& by, int& bz, int xcd)
 }
 
 // One plane's global inputs of a row-wave lane: own raw inputs at k+1 (the
-// plane above, for the z queue), apply's extras, the density at k+1, and for
-// the first / last wavefront of the block the raw inputs and density of the
-// row beyond the tile.
+// plane above, for the z queue), apply's extras, and for the first / last
+// wavefront of the block the raw inputs of the row beyond the tile; with
+// density-formed weights (finest level) the density at k+1 and of the row
+// beyond, with stored bfloat16 weights (coarse float32 levels) the cell's east,
+// north and top weights and, for the first wavefront, the north weight of the
+// row beyond (its south weight).
 template <class T, int CPT, class Raw, class Ex>
 struct RwRegs {
     Raw rn[CPT];   // raw inputs at (i, j, k+1)
     Ex ex[CPT];    // apply's extras at (i, j, k)
-    T rho_n[CPT];  // density at (i, j, k+1)
+    T rho_n[CPT];  // density at (i, j, k+1)           | bfloat16 weights: top weight at (i, j, k)
     Raw rh[CPT];   // halo row raw inputs at (i, j +- 1, k)
-    T rho_h[CPT];  // halo row density at (i, j +- 1, k)
+    T rho_h[CPT];  // halo row density at (i, j +- 1, k) | bfloat16: north weight of row j - 1
+    T w_e[CPT];    // bfloat16 weights: east and north weight at (i, j, k)
+    T w_n[CPT];
 };
 
 // The row-wave march.  Op is the same interface as for march() (pp_march.hpp):
 // load / val / extra / apply per cell; every lane calls apply for each of its
-// cells at every plane (act false outside the grid).
-template <class T, int CPT, int BY, class Op, class Acc>
+// cells at every plane (act false outside the grid).  WM: kWRho (weights from
+// the density, finest level) or kWHalf (stored bfloat16 weights).
+template <class T, int CPT, int BY, class Op, class Acc, int WM = kWRho>
 __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op, Acc& acc)
 {
+    static_assert(WM == kWRho || WM == kWHalf, "row-wave weights: density or bfloat16");
+    constexpr bool RHO = WM == kWRho;
     using Raw = typename Op::Raw;
     using Ex = typename Op::Ex;
     using Regs = RwRegs<T, CPT, Raw, Ex>;
     constexpr int NX = 64 * CPT;
     __shared__ T sv[2][BY][NX];   // stencil value of each cell, by plane parity
-    __shared__ T sr[2][BY][NX];   // density of each cell, by plane parity
+    __shared__ T sr[2][BY][NX];   // density (or north weight) of each cell, by plane parity
     const int lane = threadIdx.x, ty = threadIdx.y;
     int by, bz;
     rw_tile(by, bz, xcd);
@@ -88,14 +96,21 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             S.rn[e] = op.load(ct + e, i0 + e, jc, kt);
-            S.rho_n[e] = L.rho[ct + e];
             S.ex[e] = op.extra(c + e);
+            if constexpr (RHO) {
+                S.rho_n[e] = L.rho[ct + e];
+            } else {
+                S.w_e[e] = (T)from_bf16(L.hwx[c + e]);
+                S.w_n[e] = (T)from_bf16(L.hwy[c + e]);
+                S.rho_n[e] = (T)from_bf16(L.hwz[c + e]);
+            }
         }
         if (lo || hi) {
 #pragma unroll
             for (int e = 0; e < CPT; ++e) {
                 S.rh[e] = op.load(c + oj + e, i0 + e, jc + (lo ? -1 : 1), k);
-                S.rho_h[e] = L.rho[c + oj + e];
+                if constexpr (RHO) S.rho_h[e] = L.rho[c + oj + e];
+                else S.rho_h[e] = lo ? (T)from_bf16(L.hwy[c + oj + e]) : T(0);
             }
         }
     };
@@ -111,8 +126,13 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
             vm[e] = act ? op.val(op.load(cb + e, i0 + e, jc, kb0)) : T(0);
             rc[e] = op.load(c + e, i0 + e, jc, k0);
             vc[e] = act ? op.val(rc[e]) : T(0);
-            rho_c[e] = L.rho[c + e];
-            wb[e] = face_beta(L.rho[cb + e], rho_c[e]);
+            if constexpr (RHO) {
+                rho_c[e] = L.rho[c + e];
+                wb[e] = face_beta(L.rho[cb + e], rho_c[e]);
+            } else {
+                rho_c[e] = T(0);
+                wb[e] = (T)from_bf16(L.hwz[cb + e]);
+            }
         }
     }
     Regs R[2];
@@ -126,7 +146,8 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
         for (int e = 0; e < CPT; ++e) {
             vp[e] = act ? op.val(S.rn[e]) : T(0);
             sv[buf][ty][i0 + e] = vc[e];
-            sr[buf][ty][i0 + e] = act ? rho_c[e] : T(1);
+            if constexpr (RHO) sr[buf][ty][i0 + e] = act ? rho_c[e] : T(1);
+            else sr[buf][ty][i0 + e] = act ? S.w_n[e] : T(0);
         }
         T vh[CPT];
         if (lo || hi) {
@@ -136,12 +157,17 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
         lds_barrier();
         // x neighbours: own registers, the previous lane's last cell, the next lane's first
         const T v_prev = lane_prev(vc[CPT - 1]), v_next = lane_next(vc[0]);
-        const T r_next = lane_next(rho_c[0]);
         T we[CPT];
+        if constexpr (RHO) {
+            const T r_next = lane_next(rho_c[0]);
 #pragma unroll
-        for (int e = 0; e < CPT; ++e) {
-            const T re = e < CPT - 1 ? rho_c[e + 1] : r_next;
-            we[e] = (i0 + e < NX - 1) ? face_beta(rho_c[e], re) : T(0);
+            for (int e = 0; e < CPT; ++e) {
+                const T re = e < CPT - 1 ? rho_c[e + 1] : r_next;
+                we[e] = (i0 + e < NX - 1) ? face_beta(rho_c[e], re) : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < CPT; ++e) we[e] = S.w_e[e];  // zero on the wall face
         }
         const T we_prev = lane_prev(we[CPT - 1]);
 #pragma unroll
@@ -150,14 +176,25 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
             const T vw = e > 0 ? vc[e - 1] : v_prev;
             const T ve = e < CPT - 1 ? vc[e + 1] : v_next;
             const T ww = e > 0 ? we[e - 1] : (i > 0 ? we_prev : T(0));
-            T vs, vn, rs, rn;
-            if (ty > 0) { vs = sv[buf][ty - 1][i]; rs = sr[buf][ty - 1][i]; }
-            else { vs = lo ? vh[e] : T(0); rs = lo ? S.rho_h[e] : T(1); }
-            if (ty < BY - 1) { vn = sv[buf][ty + 1][i]; rn = sr[buf][ty + 1][i]; }
-            else { vn = hi ? vh[e] : T(0); rn = hi ? S.rho_h[e] : T(1); }
-            const T ws = in_s ? face_beta(rs, rho_c[e]) : T(0);
-            const T wn = in_n ? face_beta(rho_c[e], rn) : T(0);
-            const T wt = face_beta(rho_c[e], S.rho_n[e]);
+            T vs, vn, ws, wn, wt;
+            if constexpr (RHO) {
+                T rs, rn;
+                if (ty > 0) { vs = sv[buf][ty - 1][i]; rs = sr[buf][ty - 1][i]; }
+                else { vs = lo ? vh[e] : T(0); rs = lo ? S.rho_h[e] : T(1); }
+                if (ty < BY - 1) { vn = sv[buf][ty + 1][i]; rn = sr[buf][ty + 1][i]; }
+                else { vn = hi ? vh[e] : T(0); rn = hi ? S.rho_h[e] : T(1); }
+                ws = in_s ? face_beta(rs, rho_c[e]) : T(0);
+                wn = in_n ? face_beta(rho_c[e], rn) : T(0);
+                wt = face_beta(rho_c[e], S.rho_n[e]);
+            } else {
+                if (ty > 0) { vs = sv[buf][ty - 1][i]; ws = sr[buf][ty - 1][i]; }
+                else { vs = lo ? vh[e] : T(0); ws = lo ? S.rho_h[e] : T(0); }
+                if (ty < BY - 1) vn = sv[buf][ty + 1][i];
+                else vn = hi ? vh[e] : T(0);
+                ws = in_s ? ws : T(0);
+                wn = S.w_n[e];  // zero on the wall face
+                wt = S.rho_n[e];
+            }
             Stencil<T> st;
             st.s = ww * vw + we[e] * ve + ws * vs + wn * vn + wb[e] * vm[e] + wt * vp[e];
             st.d = ww + we[e] + ws + wn + wb[e] + wt;
@@ -175,7 +212,7 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
             vm[e] = vc[e];
             vc[e] = vp[e];
             rc[e] = S.rn[e];
-            rho_c[e] = S.rho_n[e];
+            if constexpr (RHO) rho_c[e] = S.rho_n[e];
         }
     };
 
@@ -224,6 +261,52 @@ __global__ void __launch_bounds__(64 * BY) r_apply(LevelView<double> L, const do
     OpApply<double> op{x, y, inv_h2};
     double acc[1] = {0.0};
     march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
+}
+
+// Row-wave passes of a float32 coarse level with stored bfloat16 weights (the
+// float32 cycle's large coarse levels): the same operations as m_smooth_first,
+// m_smooth_half, m_prolong_black and m_dir_apply there.
+template <int CPT, int BY>
+__global__ void __launch_bounds__(64 * BY) r_smooth_first(LevelView<float> L, const float* __restrict__ f,
+                                                         float* __restrict__ x, int kper, int xcd, float omega)
+{
+    OpFirst<float> op{f, L.invd, x, omega};
+    double acc[1] = {0.0};
+    march_rw<float, CPT, BY, OpFirst<float>, double[1], kWHalf>(L, kper, xcd, op, acc);
+}
+
+template <int CPT, int BY, int NDOT, class TQ>
+__global__ void __launch_bounds__(64 * BY) r_smooth_half(LevelView<float> L, const float* __restrict__ f, float* x,
+                                                        int colour, int kper, int xcd, const TQ* __restrict__ q, Reduce R,
+                                                        float omega)
+{
+    OpHalf<float, NDOT, TQ> op{f, x, q, colour, omega};
+    double acc[NDOT > 0 ? NDOT : 1] = {};
+    march_rw<float, CPT, BY, OpHalf<float, NDOT, TQ>, double[NDOT > 0 ? NDOT : 1], kWHalf>(L, kper, xcd, op, acc);
+    if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
+}
+
+template <int CPT, int BY>
+__global__ void __launch_bounds__(64 * BY) r_prolong_black(LevelView<float> L, const float* __restrict__ f,
+                                                          const float* __restrict__ x, const float* __restrict__ e,
+                                                          float wc, float* __restrict__ y, int kper, int xcd, float omega)
+{
+    OpProlongBlack<float> op{f, x, e, y, wc, omega, L.nx >> 1, L.ny >> 1};
+    double acc[1] = {0.0};
+    march_rw<float, CPT, BY, OpProlongBlack<float>, double[1], kWHalf>(L, kper, xcd, op, acc);
+}
+
+template <int CPT, int BY, bool BETA>
+__global__ void __launch_bounds__(64 * BY) r_dir_apply_f32(LevelView<float> L, const float* __restrict__ z,
+                                                          const float* __restrict__ dold, float* __restrict__ dnew,
+                                                          float* __restrict__ q, const float* __restrict__ r, Coefs beta,
+                                                          Coefs mean, int use_mean, int kper, int xcd, Reduce R)
+{
+    OpDir<float, float, BETA, false> op{z, dold, r, dnew, q, nullptr, BETA ? (float)beta.get() : 0.0f,
+                                        use_mean ? (float)mean.get() : 0.0f, 0.0f};
+    double acc[2] = {0.0, 0.0};
+    march_rw<float, CPT, BY, OpDir<float, float, BETA, false>, double[2], kWHalf>(L, kper, xcd, op, acc);
+    reduce_finish<2>(acc, R);
 }
 
 }  // namespace pp

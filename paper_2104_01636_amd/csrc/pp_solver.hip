@@ -256,6 +256,7 @@ struct Params {
     bool rwdir = false;         // ... and for the direction update (measured slower: 435 against 414 us)
     int rwblocks = 512;         // blocks of a row-wave launch, at most (z split to reach it)
     int rwrows = 8;             // rows (wavefronts) of a row-wave block: 4 or 8
+    bool rwc = true;            // row-wave passes on float32 coarse levels with bfloat16 weights (nx 64..256)
     bool rwf = true;            // row-wave forms of the fused float32 finest-level passes (nx 128 or 256)
     int rwfrows = 8;            // their rows per block, ring included: 8 or 16
     int rwfblocks = 512;        // their blocks per launch, at most
@@ -766,6 +767,28 @@ static RwGeo rw_geo(const Handle* H, const LevelView<double>& v)
     g.cpt = v.nx / 64;
     return g;
 }
+// Row-wave geometry of a pass on a float32 level with bfloat16 weights, or cpt = 0.
+template <class T>
+static RwGeo rwc_geo(const Handle* H, const LevelView<T>& v)
+{
+    RwGeo g;
+    if constexpr (std::is_same_v<T, float>) {
+        if (!H->prm.rwc || !H->prm.march || !v.hwx || v.nx % 64 != 0 || v.nx > 256) return g;
+        const int rows = H->prm.rwrows;
+        const int gy = (v.ny + rows - 1) / rows;
+        int gz = std::max(1, std::min(v.nz, H->prm.rwblocks / gy));
+        const int kper = (v.nz + gz - 1) / gz;
+        gz = (v.nz + kper - 1) / kper;
+        if ((size_t)gy * gz > (size_t)kMaxPartialBlocks) return g;
+        g.grid = dim3(1, gy, gz);
+        g.block = dim3(64, rows, 1);
+        g.kper = kper;
+        g.cpt = v.nx / 64;
+        g.rows = rows;
+    }
+    return g;
+}
+
 // Calls f(BxC<cpt>{}, BxC<rows>{}) for the row-wave instantiations.
 template <class F>
 static void with_cpt(const RwGeo& g, F&& f)
@@ -788,6 +811,17 @@ template <class T>
 static void launch_first(Handle* H, const LevelView<T>& v, const T* f, T* x)
 {
     const T om = (T)H->prm.omega;
+    if constexpr (std::is_same_v<T, float>) {
+        const RwGeo rg = rwc_geo(H, v);
+        if (rg.cpt) {
+            with_cpt(rg, [&](auto C, auto Y) {
+                r_smooth_first<decltype(C)::value, decltype(Y)::value>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, rg.kper, H->prm.rwxcd, om);
+            });
+            check_launch();
+            return;
+        }
+    }
     if (H->prm.march) {
         const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
@@ -809,6 +843,17 @@ template <class T, int NDOT, class TQ>
 static dim3 launch_half(Handle* H, const LevelView<T>& v, const T* f, T* x, int colour, const TQ* q, const Reduce& R)
 {
     const T om = (T)H->prm.omega;
+    if constexpr (std::is_same_v<T, float>) {
+        const RwGeo rg = rwc_geo(H, v);
+        if (rg.cpt) {
+            with_cpt(rg, [&](auto C, auto Y) {
+                r_smooth_half<decltype(C)::value, decltype(Y)::value, NDOT, TQ>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, colour, rg.kper, H->prm.rwxcd, q, R, om);
+            });
+            check_launch();
+            return rg.grid;
+        }
+    }
     if (H->prm.march) {
         const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
@@ -935,6 +980,17 @@ template <class T>
 static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, const T* x, const T* e, T wc, T* y)
 {
     const T om = (T)H->prm.omega;
+    if constexpr (std::is_same_v<T, float>) {
+        const RwGeo rg = rwc_geo(H, v);
+        if (rg.cpt) {
+            with_cpt(rg, [&](auto C, auto Y) {
+                r_prolong_black<decltype(C)::value, decltype(Y)::value>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, e, wc, y, rg.kper, H->prm.rwxcd, om);
+            });
+            check_launch();
+            return;
+        }
+    }
     if (H->prm.march) {
         const MGeo g = march_geo(H, v, H->prm.mbx);
         with_bx(g.bx, [&](auto B) {
@@ -955,6 +1011,22 @@ template <class T, class TZ, bool FINE = false>
 static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* dold, T* dnew, T* q, const T* r, T* x,
                        Coefs beta, int use_beta, Coefs mean, int use_mean, Coefs aprev, const Reduce& R)
 {
+    if constexpr (!FINE && std::is_same_v<T, float> && std::is_same_v<TZ, float>) {
+        const RwGeo rg = rwc_geo(H, v);
+        if (rg.cpt) {
+            with_cpt(rg, [&](auto C, auto Y) {
+                constexpr int CPT = decltype(C)::value, BY = decltype(Y)::value;
+                if (use_beta)
+                    r_dir_apply_f32<CPT, BY, true><<<rg.grid, rg.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, beta, mean, use_mean, rg.kper, H->prm.rwxcd, R);
+                else
+                    r_dir_apply_f32<CPT, BY, false><<<rg.grid, rg.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, beta, mean, use_mean, rg.kper, H->prm.rwxcd, R);
+            });
+            check_launch();
+            return rg.grid;
+        }
+    }
     if constexpr (FINE && std::is_same_v<T, double>) {
         const RwGeo rg = H->prm.rwdir ? rw_geo(H, v) : RwGeo{};
         if (rg.cpt) {
@@ -1561,6 +1633,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_RWXCD")) p.rwxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWROWS")) p.rwrows = atoi(s) <= 4 ? 4 : 8;
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWC")) p.rwc = atoi(s) != 0;
     if (const char* s = getenv("PP_RWFROWS")) p.rwfrows = atoi(s) >= 16 ? 16 : 8;
     if (const char* s = getenv("PP_RWFBLOCKS")) p.rwfblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBX")) {
