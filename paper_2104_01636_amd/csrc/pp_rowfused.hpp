@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
     rw_tile(by, bz, xcd);
     const int j = by * SY + ty - 1;  // rows 0 and BY-1 of the block are the ring
     const int k0 = bz * kper, k1 = min(L.nz, k0 + kper);
+    if (k0 >= k1) return;  // an empty z range (none in the launches made here)
     const bool act = j >= 0 && j < L.ny;
     const bool own = act && ty >= 1 && ty <= BY - 2;
     const int jc = max(0, min(j, L.ny - 1));
@@ -296,6 +297,13 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, co
     rw_tile(by, bz, xcd);
     const int j = by * SY + ty - 1;
     const int k0 = bz * kper, k1 = min(L.nz, k0 + kper);
+    if (k0 >= k1) {  // an empty z range (none in the launches made here): a zero partial
+        if constexpr (NDOT > 0) {
+            double zero[NDOT] = {};
+            reduce_finish<NDOT>(zero, R);
+        }
+        return;
+    }
     const bool act = j >= 0 && j < L.ny;
     const bool own = act && ty >= 1 && ty <= BY - 2;
     const int jc = max(0, min(j, L.ny - 1));

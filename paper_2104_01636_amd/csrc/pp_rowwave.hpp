@@ -79,6 +79,7 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
     rw_tile(by, bz, xcd);
     const int j = by * BY + ty;
     const int k0 = bz * kper, k1 = min(L.nz, k0 + kper);
+    if (k0 >= k1) return;  // an empty z range (none in the launches made here)
     const bool act = j < L.ny;
     const int jc = min(j, L.ny - 1);
     const int i0 = lane * CPT;
