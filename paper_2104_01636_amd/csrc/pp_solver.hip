@@ -258,8 +258,9 @@ struct Params {
     int rwrows = 8;             // rows (wavefronts) of a row-wave block: 4 or 8
     bool rwc = true;            // row-wave passes on float32 coarse levels with bfloat16 weights (nx 64..256)
     bool rwf = true;            // row-wave forms of the fused float32 finest-level passes (nx 128 or 256)
-    int rwfrows = 8;            // their rows per block, ring included: 8 or 16
-    int rwfblocks = 512;        // their blocks per launch, at most
+    int rwfrows = 12;           // their rows per block, ring included: 8, 12 or 16 (12: the most rows whose
+                                // registers (153 per lane) still fit three waves per SIMD)
+    int rwfblocks = 256;        // their blocks per launch, at most (one per CU)
     int rwfxcd = 0;             // XCD-aware band order for them (measured slower: 265 against 213 us)
     int rwxcd = 1;              // XCD-aware band order for the row-wave launches (neighbouring row bands,
                                 // whose halo rows overlap, share an L2)
@@ -928,6 +929,7 @@ static void with_cpt_even(const RwGeo& g, F&& f)
 {
     auto rows = [&](auto C) {
         if (g.rows == 16) f(C, BxC<16>{});
+        else if (g.rows == 12) f(C, BxC<12>{});
         else f(C, BxC<8>{});
     };
     if (g.cpt == 2) rows(BxC<2>{});
@@ -1648,7 +1650,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
     if (const char* s = getenv("PP_RWC")) p.rwc = atoi(s) != 0;
     if (const char* s = getenv("PP_RWFXCD")) p.rwfxcd = atoi(s) != 0;
-    if (const char* s = getenv("PP_RWFROWS")) p.rwfrows = atoi(s) >= 16 ? 16 : 8;
+    if (const char* s = getenv("PP_RWFROWS")) p.rwfrows = atoi(s) >= 16 ? 16 : (atoi(s) >= 12 ? 12 : 8);
     if (const char* s = getenv("PP_RWFBLOCKS")) p.rwfblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBX")) {
         const int b = atoi(s);

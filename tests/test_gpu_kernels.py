@@ -88,13 +88,10 @@ def test_presmooth_restrict_matches_definitions(shape, mode):
     assert ex <= TOL[mode] and er <= TOL[mode]
 
 
-@pytest.mark.parametrize("shape", SHAPES + [(512, 256, 256)])
+@pytest.mark.parametrize("shape,wc", [(sh, w) for sh in SHAPES for w in (1.0, 2.0)] + [((512, 256, 256), 1.0)])
 @pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
-@pytest.mark.parametrize("wc", [1.0, 2.0])
 def test_prolong_postsmooth_matches_definitions(shape, mode, wc):
     nz, ny, nx = shape
-    if shape == (512, 256, 256) and wc != 1.0:
-        pytest.skip("one correction scale at full size")
     say("prolong_postsmooth", shape, mode, wc)
     case = case_for(shape, 200 + sum(shape))
     rho, f, rng = inputs(case, mode, 2)
