@@ -12,7 +12,8 @@
 // stage trails the first by one plane.  Rows span the whole x extent (walls at
 // both ends), so there is no ring and no halo in x: x neighbours are in the
 // lane's registers or the next / previous lane (shuffles), y neighbours in a
-// double-buffered LDS copy of the plane (one barrier per plane), z neighbours in
+// double-buffered LDS copy of the plane (one barrier per plane; slot-major,
+// cell e of lane l at e * 64 + l, free of bank conflicts), z neighbours in
 // registers.  The ring rows also load the row beyond the tile.
 //
 // The first pass uses the red-black structure to halve its second stage: a
@@ -122,8 +123,8 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             vp[e] = act ? omega * (S.f[e] * S.d[e]) : 0.0f;
-            s_val[buf][ty][i0 + e] = vc[e];
-            s_rho[buf][ty][i0 + e] = act ? rho_c[e] : 1.0f;
+            s_val[buf][ty][e * 64 + lane] = vc[e];
+            s_rho[buf][ty][e * 64 + lane] = act ? rho_c[e] : 1.0f;
         }
         if (lo || hi) {
 #pragma unroll
@@ -134,7 +135,7 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
         if (pend_k >= 0) {
             if ((ty & 1) && own && j + 1 < L.ny) {
 #pragma unroll
-                for (int h = 0; h < HP; ++h) pend[h] += s_r[ty + 1][lane * HP + h];
+                for (int h = 0; h < HP; ++h) pend[h] += s_r[ty + 1][h * 64 + lane];
             }
             if ((ty & 1) && own) {
                 float* dst = rc + cell(cnx, cny, lane * HP, j >> 1, pend_k);
@@ -163,9 +164,9 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
             const float ve = e < CPT - 1 ? vc[e + 1] : v_next;
             const float ww = e > 0 ? we[e - 1] : (i > 0 ? we_prev : 0.0f);
             float vs, vn, rs, rn;
-            if (ty > 0) { vs = s_val[buf][ty - 1][i]; rs = s_rho[buf][ty - 1][i]; }
+            if (ty > 0) { vs = s_val[buf][ty - 1][e * 64 + lane]; rs = s_rho[buf][ty - 1][e * 64 + lane]; }
             else { vs = lo ? vh[e] : 0.0f; rs = lo ? S.rh[e] : 1.0f; }
-            if (ty < BY - 1) { vn = s_val[buf][ty + 1][i]; rn = s_rho[buf][ty + 1][i]; }
+            if (ty < BY - 1) { vn = s_val[buf][ty + 1][e * 64 + lane]; rn = s_rho[buf][ty + 1][e * 64 + lane]; }
             else { vn = hi ? vh[e] : 0.0f; rn = hi ? S.rh[e] : 1.0f; }
             const float ws = in_s ? face_beta(rs, rho_c[e]) : 0.0f;
             const float wn = in_n ? face_beta(rho_c[e], rn) : 0.0f;
@@ -190,7 +191,7 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
             for (int e = 0; e < CPT; ++e) x[c + e] = x1[e];
         }
 #pragma unroll
-        for (int e = 0; e < CPT; ++e) s_x[buf][ty][i0 + e] = x1[e];
+        for (int e = 0; e < CPT; ++e) s_x[buf][ty][e * 64 + lane] = x1[e];
         // second stage at plane k-1 (a real plane from v = k0 + 1 on): residual of its red cells
         // from the new x of their black neighbours, then the restriction
         if (v >= k0 + 1) {
@@ -207,8 +208,8 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
                     const int hh = e >> 1;
                     const float xw = e > 0 ? xm1[e - 1] : x_prev;
                     const float xe = e < CPT - 1 ? xm1[e + 1] : x_next;
-                    const float xs = ty > 0 ? s_x[bm][ty - 1][i] : 0.0f;
-                    const float xn = ty < BY - 1 ? s_x[bm][ty + 1][i] : 0.0f;
+                    const float xs = ty > 0 ? s_x[bm][ty - 1][e * 64 + lane] : 0.0f;
+                    const float xn = ty < BY - 1 ? s_x[bm][ty + 1][e * 64 + lane] : 0.0f;
                     const float s = ws6[hh][0] * xw + ws6[hh][1] * xe + ws6[hh][2] * xs + ws6[hh][3] * xn +
                                     ws6[hh][4] * xm2[e] + ws6[hh][5] * x1[e];
                     r[e] = (1.0f - omega) * fr[hh] + s;
@@ -228,7 +229,7 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
                 for (int q = 0; q < HP; ++q) pend[q] = part[q] + p[q];
                 if (!(ty & 1)) {
 #pragma unroll
-                    for (int q = 0; q < HP; ++q) s_r[ty][lane * HP + q] = pend[q];
+                    for (int q = 0; q < HP; ++q) s_r[ty][q * 64 + lane] = pend[q];
                 }
                 pend_k = km >> 1;
             }
@@ -266,7 +267,7 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
         if ((ty & 1) && own) {
             if (j + 1 < L.ny) {
 #pragma unroll
-                for (int h = 0; h < HP; ++h) pend[h] += s_r[ty + 1][lane * HP + h];
+                for (int h = 0; h < HP; ++h) pend[h] += s_r[ty + 1][h * 64 + lane];
             }
             float* dst = rc + cell(cnx, cny, lane * HP, j >> 1, pend_k);
 #pragma unroll
@@ -379,8 +380,8 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, co
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             vp[e] = act ? S.x[e] + wc * S.e[e >> 1] : 0.0f;
-            s_val[buf][ty][i0 + e] = vc[e];
-            s_rho[buf][ty][i0 + e] = act ? rho_c[e] : 1.0f;
+            s_val[buf][ty][e * 64 + lane] = vc[e];
+            s_rho[buf][ty][e * 64 + lane] = act ? rho_c[e] : 1.0f;
         }
         if (lo || hi) {
 #pragma unroll
@@ -407,9 +408,9 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, co
             const float ve = e < CPT - 1 ? vc[e + 1] : v_next;
             const float ww = e > 0 ? we[e - 1] : (i > 0 ? we_prev : 0.0f);
             float vs, vn, rs, rn;
-            if (ty > 0) { vs = s_val[buf][ty - 1][i]; rs = s_rho[buf][ty - 1][i]; }
+            if (ty > 0) { vs = s_val[buf][ty - 1][e * 64 + lane]; rs = s_rho[buf][ty - 1][e * 64 + lane]; }
             else { vs = lo ? vh[e] : 0.0f; rs = lo ? S.rh[e] : 1.0f; }
-            if (ty < BY - 1) { vn = s_val[buf][ty + 1][i]; rn = s_rho[buf][ty + 1][i]; }
+            if (ty < BY - 1) { vn = s_val[buf][ty + 1][e * 64 + lane]; rn = s_rho[buf][ty + 1][e * 64 + lane]; }
             else { vn = hi ? vh[e] : 0.0f; rn = hi ? S.rh[e] : 1.0f; }
             const float ws = in_s ? face_beta(rs, rho_c[e]) : 0.0f;
             const float wn = in_n ? face_beta(rho_c[e], rn) : 0.0f;
@@ -427,7 +428,7 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, co
             wb[e] = wt;
         }
 #pragma unroll
-        for (int e = 0; e < CPT; ++e) s_y[buf][ty][i0 + e] = y1[e];
+        for (int e = 0; e < CPT; ++e) s_y[buf][ty][e * 64 + lane] = y1[e];
         // second stage at plane k-1 (real from v = k0 + 1 on): red cells one SOR update from
         // their black neighbours' y; write z and reduce the dots
         if (v >= k0 + 1) {
@@ -444,8 +445,8 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, co
                     const int hh = e >> 1;
                     const float yw = e > 0 ? ym1[e - 1] : y_prev;
                     const float ye = e < CPT - 1 ? ym1[e + 1] : y_next;
-                    const float ys = ty > 0 ? s_y[bm][ty - 1][i] : 0.0f;
-                    const float yn = ty < BY - 1 ? s_y[bm][ty + 1][i] : 0.0f;
+                    const float ys = ty > 0 ? s_y[bm][ty - 1][e * 64 + lane] : 0.0f;
+                    const float yn = ty < BY - 1 ? s_y[bm][ty + 1][e * 64 + lane] : 0.0f;
                     const float s = ws6[hh][0] * yw + ws6[hh][1] * ye + ws6[hh][2] * ys + ws6[hh][3] * yn +
                                     ws6[hh][4] * ym2[e] + ws6[hh][5] * y1[e];
                     const float d = ws6[hh][0] + ws6[hh][1] + ws6[hh][2] + ws6[hh][3] + ws6[hh][4] + ws6[hh][5];

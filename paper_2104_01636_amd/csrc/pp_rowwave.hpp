@@ -9,7 +9,10 @@
 //     row, so there is no x halo at all (on a tiled row every tile edge would
 //     fetch a whole cache line for one element per array and plane);
 //   * y neighbours of the block's inner rows come from a double-buffered LDS
-//     copy of the plane (one barrier per plane); the first and last row of the
+//     copy of the plane (one barrier per plane), stored slot-major: cell e of
+//     lane l at e * 64 + l, so that the wavefront's access to one slot is 64
+//     consecutive elements and no two lanes meet in an LDS bank (lane-major,
+//     l * CPT + e, put CPT lanes on each bank); the first and last row of the
 //     block (whole wavefronts, so the branch is uniform) also load the row
 //     beyond the tile, one full row per array;
 //   * z neighbours come from a three-plane register queue, as in pp_march.hpp;
@@ -27,11 +30,33 @@
 
 namespace pp {
 
-// Shuffles of a value one lane down (lane l gets lane l+1's value) and up.
+// Shifts of a value across the wavefront: lane l gets lane l+1's value
+// (lane_next) or lane l-1's (lane_prev); the edge lane keeps its own.  DPP
+// wave shifts (wave_shl:1 = 0x130, wave_shr:1 = 0x138) move 32 bits per VALU
+// move without the LDS crossbar a bpermute takes; a double moves as two halves.
+// Callers are in wavefront-uniform control flow (every lane active).
+template <int CTRL>
+__device__ inline int wave_shift32(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ inline float wave_shift(float v)
+{
+    return __int_as_float(wave_shift32<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ inline double wave_shift(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = wave_shift32<CTRL>((int)(b & 0xffffffffll));
+    const int hi = wave_shift32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 template <class T>
-__device__ inline T lane_next(T v) { return __shfl_down(v, 1, 64); }
+__device__ inline T lane_next(T v) { return wave_shift<0x130>(v); }
 template <class T>
-__device__ inline T lane_prev(T v) { return __shfl_up(v, 1, 64); }
+__device__ inline T lane_prev(T v) { return wave_shift<0x138>(v); }
 
 // Tile (row band and z range) of this block: grid.y bands of SY rows, grid.z
 // z ranges, blocks dealt to the XCDs in contiguous runs (see tile_of_block).
@@ -146,9 +171,9 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             vp[e] = act ? op.val(S.rn[e]) : T(0);
-            sv[buf][ty][i0 + e] = vc[e];
-            if constexpr (RHO) sr[buf][ty][i0 + e] = act ? rho_c[e] : T(1);
-            else sr[buf][ty][i0 + e] = act ? S.w_n[e] : T(0);
+            sv[buf][ty][e * 64 + lane] = vc[e];
+            if constexpr (RHO) sr[buf][ty][e * 64 + lane] = act ? rho_c[e] : T(1);
+            else sr[buf][ty][e * 64 + lane] = act ? S.w_n[e] : T(0);
         }
         T vh[CPT];
         if (lo || hi) {
@@ -180,17 +205,17 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
             T vs, vn, ws, wn, wt;
             if constexpr (RHO) {
                 T rs, rn;
-                if (ty > 0) { vs = sv[buf][ty - 1][i]; rs = sr[buf][ty - 1][i]; }
+                if (ty > 0) { vs = sv[buf][ty - 1][e * 64 + lane]; rs = sr[buf][ty - 1][e * 64 + lane]; }
                 else { vs = lo ? vh[e] : T(0); rs = lo ? S.rho_h[e] : T(1); }
-                if (ty < BY - 1) { vn = sv[buf][ty + 1][i]; rn = sr[buf][ty + 1][i]; }
+                if (ty < BY - 1) { vn = sv[buf][ty + 1][e * 64 + lane]; rn = sr[buf][ty + 1][e * 64 + lane]; }
                 else { vn = hi ? vh[e] : T(0); rn = hi ? S.rho_h[e] : T(1); }
                 ws = in_s ? face_beta(rs, rho_c[e]) : T(0);
                 wn = in_n ? face_beta(rho_c[e], rn) : T(0);
                 wt = face_beta(rho_c[e], S.rho_n[e]);
             } else {
-                if (ty > 0) { vs = sv[buf][ty - 1][i]; ws = sr[buf][ty - 1][i]; }
+                if (ty > 0) { vs = sv[buf][ty - 1][e * 64 + lane]; ws = sr[buf][ty - 1][e * 64 + lane]; }
                 else { vs = lo ? vh[e] : T(0); ws = lo ? S.rho_h[e] : T(0); }
-                if (ty < BY - 1) vn = sv[buf][ty + 1][i];
+                if (ty < BY - 1) vn = sv[buf][ty + 1][e * 64 + lane];
                 else vn = hi ? vh[e] : T(0);
                 ws = in_s ? ws : T(0);
                 wn = S.w_n[e];  // zero on the wall face
