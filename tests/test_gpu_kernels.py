@@ -44,10 +44,12 @@ def host(t):
 
 
 # (nz, ny, nx): grids that coarsen; 32x32x64 and 256x256x512 run the fused float32
-# kernels, 64x64x128 (524288 cells) their unfused passes; rows of 256 and 128 cells
-# run the row-wave forms of the fused kernels (a wavefront per row), here with a
-# partial last band of rows
-SHAPES = [(8, 6, 10), (12, 10, 6), (16, 8, 8), (64, 32, 32), (128, 64, 64), (8, 10, 256), (16, 24, 128)]
+# kernels, 64x64x128 (524288 cells) their unfused passes; rows of 256, 128 and 64
+# cells run the row-wave forms of the fused kernels (a wavefront per row; with 64,
+# one cell per lane and the x pairs across lane pairs), here with a partial last
+# band of rows
+SHAPES = [(8, 6, 10), (12, 10, 6), (16, 8, 8), (64, 32, 32), (128, 64, 64), (8, 10, 256), (16, 24, 128),
+          (16, 22, 64)]
 
 
 def case_for(shape, seed):
