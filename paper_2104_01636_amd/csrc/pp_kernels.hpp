@@ -407,10 +407,11 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restri
 
 // ---------------------------------------------------------------- float64 outer pieces
 
-// r = f - K x in float64; reduces ||r||^2 and sum(r).
+// r = f - K x in float64; reduces ||r||^2 and sum(r); xc (or null) receives a
+// copy of x, r32 (or null) the float32 copy of r.
 __global__ void __launch_bounds__(kBlock) k_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                          const double* __restrict__ x, double* __restrict__ r, int kper,
-                                                         Reduce R)
+                                                         Reduce R, double* __restrict__ xc, float* __restrict__ r32)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
     double acc[2] = {0.0, 0.0};
@@ -421,6 +422,8 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(LevelView<double> L, c
             nbsum<double>(L, t.i, t.j, k, c, [&](int m, int, int, int) { return x[m]; }, s, d);
             const double rv = f[c] - (d * x[c] - s);
             r[c] = rv;
+            if (xc) xc[c] = x[c];
+            if (r32) r32[c] = (float)rv;
             acc[0] += rv * rv;
             acc[1] += rv;
         }
@@ -458,13 +461,6 @@ __global__ void __launch_bounds__(kBlock) k_shift_scale(int n, const double* __r
     if (want_red) reduce_finish<1>(acc, R);
 }
 
-// r32 = (float) r64
-__global__ void __launch_bounds__(kBlock) k_demote(int n, const double* __restrict__ r, float* __restrict__ r32)
-{
-    const int stride = gridDim.x * blockDim.x;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) r32[c] = (float)r[c];
-}
-
 // ---------------------------------------------------------------- set-up
 
 // Finest-level face weights beta_f = 2/(rho_L + rho_R): IEEE division, zero on
@@ -483,6 +479,78 @@ __global__ void __launch_bounds__(kBlock) k_fine_faces(int nx, int ny, int nz, c
         wx[c] = t.i < nx - 1 ? 2.0 / (rc + rho[c + 1]) : 0.0;
         wy[c] = t.j < ny - 1 ? 2.0 / (rc + rho[c + sy]) : 0.0;
         wz[c] = 2.0 / (rc + rho[ct]);
+    }
+}
+
+// The handle's copies of the density: float64 and, for a float32 preconditioner,
+// float32 (one pass over the caller's array).
+__global__ void __launch_bounds__(kBlock) k_take_density(int n, const double* __restrict__ rho, double* __restrict__ rho64,
+                                                        float* __restrict__ rho32)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const double v = rho[c];
+        rho64[c] = v;
+        if (rho32) rho32[c] = (float)v;
+    }
+}
+
+// 1/D of the finest level straight from the density, for the kernels that form
+// their weights from it (no stored finest-level weights): D is the sum of
+// beta_f = 2/(rho_L + rho_R) over the cell's faces, added in the order nbsum
+// adds them, so the values equal those k_level_finish forms from k_fine_faces'
+// weights, bit for bit.
+__global__ void __launch_bounds__(kBlock) k_fine_diag(int nx, int ny, int nz, const double* __restrict__ rho,
+                                                     double* __restrict__ invd64, float* __restrict__ invd32, int kper)
+{
+    Tile t = tile(nx, ny, nz, kper);
+    if (!t.act) return;
+    const int sy = nx, sz = nx * ny;
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int c = cell(nx, ny, t.i, t.j, k);
+        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz, ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
+        const double r = rho[c];
+        double d = 0.0;
+        if (t.i > 0) d += 2.0 / (rho[c - 1] + r);
+        if (t.i < nx - 1) d += 2.0 / (r + rho[c + 1]);
+        if (t.j > 0) d += 2.0 / (rho[c - sy] + r);
+        if (t.j < ny - 1) d += 2.0 / (r + rho[c + sy]);
+        d += 2.0 / (rho[cb] + r);
+        d += 2.0 / (r + rho[ct]);
+        const double inv = 1.0 / d;
+        if (invd64) invd64[c] = inv;
+        if (invd32) invd32[c] = (float)inv;
+    }
+}
+
+// The first coarse level's face weights straight from the finest density: each
+// is the sum of the four fine beta_f that form it, formed and added as
+// k_fine_faces and k_coarsen form and add them (the same values, bit for bit).
+__global__ void __launch_bounds__(kBlock) k_coarsen_rho(int nx, int ny, int nz, const double* __restrict__ rho, int cnx,
+                                                       int cny, int cnz, double* __restrict__ wx, double* __restrict__ wy,
+                                                       double* __restrict__ wz, int kper)
+{
+    Tile t = tile(cnx, cny, cnz, kper);
+    if (!t.act) return;
+    const int sy = nx, sz = nx * ny;
+    for (int K = t.k0; K < t.k1; ++K) {
+        double sx = 0.0, syw = 0.0, szw = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const int i = 2 * t.i + 1, j = 2 * t.j + a, k = 2 * K + b;
+                const int c = cell(nx, ny, i, j, k);
+                sx += i < nx - 1 ? 2.0 / (rho[c] + rho[c + 1]) : 0.0;
+                const int cy = cell(nx, ny, 2 * t.i + a, 2 * t.j + 1, 2 * K + b);
+                syw += 2 * t.j + 1 < ny - 1 ? 2.0 / (rho[cy] + rho[cy + sy]) : 0.0;
+                const int kz = 2 * K + 1;
+                const int cz = cell(nx, ny, 2 * t.i + a, 2 * t.j + b, kz);
+                const int czt = kz < nz - 1 ? cz + sz : cz - (nz - 1) * sz;
+                szw += 2.0 / (rho[cz] + rho[czt]);
+            }
+        const int cc = cell(cnx, cny, t.i, t.j, K);
+        wx[cc] = sx;
+        wy[cc] = syw;
+        wz[cc] = szw;
     }
 }
 

@@ -382,10 +382,12 @@ struct OpDir {
 };
 
 template <class T>
-struct OpResidual {  // r = f - K x; dots ||r||^2, sum r
+struct OpResidual {  // r = f - K x; dots ||r||^2, sum r; optionally a copy of x and a float32 copy of r
     const T* f;
     const T* x;
     T* r;
+    T* xc = nullptr;       // receives x (or null)
+    float* r32 = nullptr;  // receives (float) r (or null)
     using Raw = T;
     using Ex = T;
     __device__ Raw load(int c, int, int, int) const { return x[c]; }
@@ -397,6 +399,8 @@ struct OpResidual {  // r = f - K x; dots ||r||^2, sum r
         if (!act) return;
         const T rv = fc - (st.d * vc - st.s);
         r[c] = rv;
+        if (xc) xc[c] = vc;
+        if (r32) r32[c] = (float)rv;
         acc[0] += (double)rv * (double)rv;
         acc[1] += (double)rv;
     }
@@ -717,9 +721,9 @@ __global__ void __launch_bounds__((kMarchThreads<double, true>)) m_rel_residual(
 template <int BX, int WM>
 __global__ void __launch_bounds__((kMarchThreads<double, WM == kWRho>)) m_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                          const double* __restrict__ x, double* __restrict__ r, int kper, int xcd,
-                                                         Reduce R)
+                                                         Reduce R, double* __restrict__ xc, float* __restrict__ r32)
 {
-    OpResidual<double> op{f, x, r};
+    OpResidual<double> op{f, x, r, xc, r32};
     double acc[2] = {0.0, 0.0};
     march<double, BX, WM>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);

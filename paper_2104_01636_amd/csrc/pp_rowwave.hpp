@@ -272,9 +272,10 @@ __global__ void __launch_bounds__(64 * BY) r_dir_apply(LevelView<double> L, cons
 template <int CPT, int BY>
 __global__ void __launch_bounds__(64 * BY) r_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                           const double* __restrict__ x, double* __restrict__ r, int kper,
-                                                          int xcd, Reduce R)
+                                                          int xcd, Reduce R, double* __restrict__ xc,
+                                                          float* __restrict__ r32)
 {
-    OpResidual<double> op{f, x, r};
+    OpResidual<double> op{f, x, r, xc, r32};
     double acc[2] = {0.0, 0.0};
     march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);

@@ -457,6 +457,12 @@ static void levels_of(const pp_config& cfg, std::vector<int>& nx, std::vector<in
     }
 }
 
+// Whether every pass on the finest level forms its face weights from the
+// density (the plane-marching kernels with density weights): the level then
+// keeps no stored weights, and the set-up forms its 1/D and the first coarse
+// level's weights from the density directly.
+static bool weights_from_density(const Params& prm) { return prm.march && prm.rho; }
+
 // Lays out (or counts) every device array of a handle.
 static size_t plan(Handle* H, const pp_config& cfg, char* base)
 {
@@ -471,17 +477,24 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
 
     // face weights of every level (level 0: beta_f) in float64, and in the
     // preconditioner's precision when that is float32; 1/D in that precision
+    // (level 0 has none when every finest-level pass forms them from the density)
     std::vector<Level64> c64(nl);
     std::vector<Level32> c32(nl);
+    const bool fine_rho = weights_from_density(prm);
     for (int l = 0; l < nl; ++l) {
-        c64[l].wx = P.take<double>(nn(l));
-        c64[l].wy = P.take<double>(nn(l));
-        c64[l].wz = P.take<double>(nn(l));
+        const bool stored = l > 0 || !fine_rho;
+        if (stored) {
+            c64[l].wx = P.take<double>(nn(l));
+            c64[l].wy = P.take<double>(nn(l));
+            c64[l].wz = P.take<double>(nn(l));
+        }
         if (fp64) c64[l].invd = P.take<double>(nn(l));
         if (!fp64) {
-            c32[l].wx = P.take<float>(nn(l));
-            c32[l].wy = P.take<float>(nn(l));
-            c32[l].wz = P.take<float>(nn(l));
+            if (stored) {
+                c32[l].wx = P.take<float>(nn(l));
+                c32[l].wy = P.take<float>(nn(l));
+                c32[l].wz = P.take<float>(nn(l));
+            }
             c32[l].invd = P.take<float>(nn(l));
             if (l >= 1 && prm.hw && (long)nn(l) > prm.hwmin) {
                 c32[l].hx = P.take<unsigned short>(nn(l));
@@ -1438,16 +1451,24 @@ static void set_density(Handle* H, const double* rho)
         throw Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
                                          " entries that are not finite or not > 0");
     // the handle's own copies of the density (the caller keeps rho)
-    PP_HIP(hipMemcpyAsync(H->rho64, rho, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
-    if (H->rho32) {
-        k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->rho64, H->rho32);
-        check_launch();
-    }
+    k_take_density<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, H->rho64, H->rho32);
+    check_launch();
+    const bool fine_rho = weights_from_density(H->prm);
     for (int l = 0; l < nl; ++l) {
         Geo g = geo(H->lnx[l], H->lny[l], H->lnz[l]);
+        if (l == 0 && fine_rho) {
+            // no stored finest weights: 1/D from the density
+            k_fine_diag<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, H->rho64, H->c64[0].invd,
+                                                           H->c32[0].invd, g.kper);
+            check_launch();
+            continue;
+        }
         if (l == 0)
             k_fine_faces<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, rho, H->c64[0].wx, H->c64[0].wy,
                                                             H->c64[0].wz, g.kper);
+        else if (l == 1 && fine_rho)
+            k_coarsen_rho<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, H->rho64, H->lnx[1], H->lny[1],
+                                                             H->lnz[1], H->c64[1].wx, H->c64[1].wy, H->c64[1].wz, g.kper);
         else
             k_coarsen<<<g.grid, g.block, 0, H->stream>>>(H->lnx[l - 1], H->lny[l - 1], H->lnz[l - 1], H->c64[l - 1].wx,
                                                          H->c64[l - 1].wy, H->c64[l - 1].wz, H->lnx[l], H->lny[l], H->lnz[l],
@@ -1492,21 +1513,24 @@ static double prepare_rhs(Handle* H, const double* rhs)
     return std::sqrt(H->host_slots[G_FN2]);
 }
 
-// r64 = f64 - K x in float64; returns ||r|| (sum(r) in slot G_TRSUM).
-static double true_residual(Handle* H, const double* x)
+// r64 = f64 - K x in float64; returns ||r|| (sum(r) in slot G_TRSUM).  xc (or
+// null) receives a copy of x, r32 (or null) the float32 copy of r.
+static double true_residual(Handle* H, const double* x, double* xc, float* r32)
 {
     const pp_config& cfg = H->cfg;
     const LevelView<double> v = fine64(H);
     dim3 grid;
     {
-        // reads f, x and the float64 weights (or density); writes r
-        TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL), (double)cfg.nx * cfg.ny * cfg.nz * (24.0 + 8.0 * weight_arrays(H, v)));
+        // reads f, x and the float64 weights (or density); writes r (and the copies)
+        TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL),
+                     (double)cfg.nx * cfg.ny * cfg.nz *
+                         (24.0 + 8.0 * weight_arrays(H, v) + (xc ? 8.0 : 0.0) + (r32 ? 4.0 : 0.0)));
         const Reduce R = red(H, G_TRR, G_TRSUM);
         const RwGeo rg = rw_geo(H, v);
         if (rg.cpt) {
             with_cpt(rg, [&](auto C, auto Y) {
                 r_true_residual<decltype(C)::value, decltype(Y)::value>
-                    <<<rg.grid, rg.block, 0, H->stream>>>(v, H->f64, x, H->r64, rg.kper, H->prm.rwxcd, R);
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, H->f64, x, H->r64, rg.kper, H->prm.rwxcd, R, xc, r32);
             });
             grid = rg.grid;
         } else if (H->prm.march) {
@@ -1514,13 +1538,13 @@ static double true_residual(Handle* H, const double* x)
             with_bx(g.bx, [&](auto B) {
                 with_rho(v, [&](auto W) {
                     m_true_residual<decltype(B)::value, decltype(W)::value>
-                        <<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, xcd_of(H, v), R);
+                        <<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, xcd_of(H, v), R, xc, r32);
                 });
             });
             grid = g.grid;
         } else {
             const Geo g = geo(cfg.nx, cfg.ny, cfg.nz);
-            k_true_residual<<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, R);
+            k_true_residual<<<g.grid, g.block, 0, H->stream>>>(v, H->f64, x, H->r64, g.kper, R, xc, r32);
             grid = g.grid;
         }
         check_launch();
@@ -1530,13 +1554,14 @@ static double true_residual(Handle* H, const double* x)
     return std::sqrt(std::max(0.0, H->host_slots[G_TRR]));
 }
 
-static void remove_mean(Handle* H, double* x)
+// out = x - mean(x) (out may be x)
+static void remove_mean(Handle* H, const double* x, double* out)
 {
     const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
     k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, 0, red(H, G_XSUM, G_XBAD));
     check_launch();
     finish(H, red(H, G_XSUM, G_XBAD), lin_grid(n0), 2);
-    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, x, 1.0, coef(H, G_XSUM, -1, 1.0 / (double)n0), 0,
+    k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, out, 1.0, coef(H, G_XSUM, -1, 1.0 / (double)n0), 0,
                                                           red(H, G_FN2));
     check_launch();
 }
@@ -1555,10 +1580,13 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
         PP_HIP(hipMemsetAsync(p, 0, sizeof(double) * n0, H->stream));
         PP_HIP(hipStreamSynchronize(H->stream));
     } else {
-        PP_HIP(hipMemcpyAsync(H->x64, p, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
         converged = false;
+        bool first = true;
         for (;;) {
-            const double rn = true_residual(H, H->x64);  // r64 = f - K x
+            // r64 = f - K x (and its float32 copy for a float32 cycle); the first one reads the
+            // caller's guess and leaves the handle's copy of it in x64
+            const double rn = first ? true_residual(H, p, H->x64, H->r32) : true_residual(H, H->x64, nullptr, H->r32);
+            first = false;
             rel = rn / fn;
             if (rel <= cfg.tol) { converged = true; break; }
             if (!(rel == rel)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
@@ -1573,18 +1601,14 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
                 ++iters;
                 continue;
             }
-            if (H->r32) {  // float32 copy of the residual for the float32 preconditioner
-                k_demote<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->r64, H->r32);
-                check_launch();
-            }
             if (cfg.mode == PP_FP64) iters += fcg(H, H->h64, cfg.tol * fn, max_it - iters, nullptr);
             else iters += fcg(H, H->h32, cfg.tol * fn, max_it - iters, nullptr);
             ++restarts;  // the recursion's residual met the tolerance: check the true one
         }
-        remove_mean(H, H->x64);
-        rel = true_residual(H, H->x64) / fn;
+        // p = x - mean(x), and the final float64 residual of p
+        remove_mean(H, H->x64, p);
+        rel = true_residual(H, p, nullptr, nullptr) / fn;
         converged = converged || rel <= cfg.tol;
-        PP_HIP(hipMemcpyAsync(p, H->x64, n0 * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
     }
     PP_HIP(hipStreamSynchronize(H->stream));
     auto t1 = std::chrono::steady_clock::now();
