@@ -87,19 +87,25 @@ struct RwRegs {
 // The row-wave march.  Op is the same interface as for march() (pp_march.hpp):
 // load / val / extra / apply per cell; every lane calls apply for each of its
 // cells at every plane (act false outside the grid).  WM: kWRho (weights from
-// the density, finest level) or kWHalf (stored bfloat16 weights).
-template <class T, int CPT, int BY, class Op, class Acc, int WM = kWRho>
+// the density, finest level) or kWHalf (stored bfloat16 weights).  WPR: the
+// wavefronts a row is split over (density weights only): lane l of the row
+// (threadIdx.x) owns cells l * CPT ..; across the boundary between two of its
+// wavefronts the x neighbour's value and density come from the row's LDS copy.
+template <class T, int CPT, int BY, class Op, class Acc, int WM = kWRho, int WPR = 1>
 __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op, Acc& acc)
 {
     static_assert(WM == kWRho || WM == kWHalf, "row-wave weights: density or bfloat16");
+    static_assert(WPR == 1 || WM == kWRho, "split rows take their x neighbours' weights from the density");
     constexpr bool RHO = WM == kWRho;
     using Raw = typename Op::Raw;
     using Ex = typename Op::Ex;
     using Regs = RwRegs<T, CPT, Raw, Ex>;
-    constexpr int NX = 64 * CPT;
-    __shared__ T sv[2][BY][NX];   // stencil value of each cell, by plane parity
+    constexpr int NL = 64 * WPR;  // lanes per row
+    constexpr int NX = NL * CPT;
+    __shared__ T sv[2][BY][NX];   // stencil value of each cell, by plane parity (cell e of lane l at e * NL + l)
     __shared__ T sr[2][BY][NX];   // density (or north weight) of each cell, by plane parity
     const int lane = threadIdx.x, ty = threadIdx.y;
+    const int wl = lane & 63, wr = lane >> 6;  // lane in its wavefront, wavefront in the row
     int by, bz;
     rw_tile(by, bz, xcd);
     const int j = by * BY + ty;
@@ -171,9 +177,9 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             vp[e] = act ? op.val(S.rn[e]) : T(0);
-            sv[buf][ty][e * 64 + lane] = vc[e];
-            if constexpr (RHO) sr[buf][ty][e * 64 + lane] = act ? rho_c[e] : T(1);
-            else sr[buf][ty][e * 64 + lane] = act ? S.w_n[e] : T(0);
+            sv[buf][ty][e * NL + lane] = vc[e];
+            if constexpr (RHO) sr[buf][ty][e * NL + lane] = act ? rho_c[e] : T(1);
+            else sr[buf][ty][e * NL + lane] = act ? S.w_n[e] : T(0);
         }
         T vh[CPT];
         if (lo || hi) {
@@ -182,10 +188,18 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
         }
         lds_barrier();
         // x neighbours: own registers, the previous lane's last cell, the next lane's first
-        const T v_prev = lane_prev(vc[CPT - 1]), v_next = lane_next(vc[0]);
+        // (across a wavefront boundary of a split row: the row's LDS copy)
+        T v_prev = lane_prev(vc[CPT - 1]), v_next = lane_next(vc[0]);
+        if constexpr (WPR > 1) {
+            if (wl == 0 && wr > 0) v_prev = sv[buf][ty][(CPT - 1) * NL + lane - 1];
+            if (wl == 63 && wr < WPR - 1) v_next = sv[buf][ty][lane + 1];
+        }
         T we[CPT];
         if constexpr (RHO) {
-            const T r_next = lane_next(rho_c[0]);
+            T r_next = lane_next(rho_c[0]);
+            if constexpr (WPR > 1) {
+                if (wl == 63 && wr < WPR - 1) r_next = sr[buf][ty][lane + 1];
+            }
 #pragma unroll
             for (int e = 0; e < CPT; ++e) {
                 const T re = e < CPT - 1 ? rho_c[e + 1] : r_next;
@@ -195,7 +209,10 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
 #pragma unroll
             for (int e = 0; e < CPT; ++e) we[e] = S.w_e[e];  // zero on the wall face
         }
-        const T we_prev = lane_prev(we[CPT - 1]);
+        T we_prev = lane_prev(we[CPT - 1]);
+        if constexpr (WPR > 1) {  // the west neighbour's east weight, formed as it forms it
+            if (wl == 0 && wr > 0) we_prev = face_beta(sr[buf][ty][(CPT - 1) * NL + lane - 1], rho_c[0]);
+        }
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             const int i = i0 + e;
@@ -205,17 +222,17 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
             T vs, vn, ws, wn, wt;
             if constexpr (RHO) {
                 T rs, rn;
-                if (ty > 0) { vs = sv[buf][ty - 1][e * 64 + lane]; rs = sr[buf][ty - 1][e * 64 + lane]; }
+                if (ty > 0) { vs = sv[buf][ty - 1][e * NL + lane]; rs = sr[buf][ty - 1][e * NL + lane]; }
                 else { vs = lo ? vh[e] : T(0); rs = lo ? S.rho_h[e] : T(1); }
-                if (ty < BY - 1) { vn = sv[buf][ty + 1][e * 64 + lane]; rn = sr[buf][ty + 1][e * 64 + lane]; }
+                if (ty < BY - 1) { vn = sv[buf][ty + 1][e * NL + lane]; rn = sr[buf][ty + 1][e * NL + lane]; }
                 else { vn = hi ? vh[e] : T(0); rn = hi ? S.rho_h[e] : T(1); }
                 ws = in_s ? face_beta(rs, rho_c[e]) : T(0);
                 wn = in_n ? face_beta(rho_c[e], rn) : T(0);
                 wt = face_beta(rho_c[e], S.rho_n[e]);
             } else {
-                if (ty > 0) { vs = sv[buf][ty - 1][e * 64 + lane]; ws = sr[buf][ty - 1][e * 64 + lane]; }
+                if (ty > 0) { vs = sv[buf][ty - 1][e * NL + lane]; ws = sr[buf][ty - 1][e * NL + lane]; }
                 else { vs = lo ? vh[e] : T(0); ws = lo ? S.rho_h[e] : T(0); }
-                if (ty < BY - 1) vn = sv[buf][ty + 1][e * 64 + lane];
+                if (ty < BY - 1) vn = sv[buf][ty + 1][e * NL + lane];
                 else vn = hi ? vh[e] : T(0);
                 ws = in_s ? ws : T(0);
                 wn = S.w_n[e];  // zero on the wall face
@@ -255,8 +272,8 @@ constexpr int kRwRowsMax = 8;
 
 // Row-wave variants of the finest-level float64 passes of the Krylov step
 // (same operations and reductions as m_dir_apply, m_true_residual, m_apply).
-template <int CPT, int BY, class TZ, bool BETA, bool FINE>
-__global__ void __launch_bounds__(64 * BY) r_dir_apply(LevelView<double> L, const TZ* __restrict__ z,
+template <int CPT, int BY, class TZ, bool BETA, bool FINE, int WPR = 1>
+__global__ void __launch_bounds__(64 * WPR * BY) r_dir_apply(LevelView<double> L, const TZ* __restrict__ z,
                                                       const double* __restrict__ dold, double* __restrict__ dnew,
                                                       double* __restrict__ q, const double* __restrict__ r,
                                                       double* __restrict__ x, Coefs beta, Coefs mean, int use_mean,
@@ -265,29 +282,29 @@ __global__ void __launch_bounds__(64 * BY) r_dir_apply(LevelView<double> L, cons
     OpDir<double, TZ, BETA, FINE> op{z, dold, r, dnew, q, x, BETA ? beta.get() : 0.0, use_mean ? mean.get() : 0.0,
                                      (FINE && BETA) ? aprev.get() : 0.0};
     double acc[2] = {0.0, 0.0};
-    march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
+    march_rw<double, CPT, BY, decltype(op), double[2], kWRho, WPR>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 
-template <int CPT, int BY>
-__global__ void __launch_bounds__(64 * BY) r_true_residual(LevelView<double> L, const double* __restrict__ f,
+template <int CPT, int BY, int WPR = 1>
+__global__ void __launch_bounds__(64 * WPR * BY) r_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                           const double* __restrict__ x, double* __restrict__ r, int kper,
                                                           int xcd, Reduce R, double* __restrict__ xc,
                                                           float* __restrict__ r32)
 {
     OpResidual<double> op{f, x, r, xc, r32};
     double acc[2] = {0.0, 0.0};
-    march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
+    march_rw<double, CPT, BY, decltype(op), double[2], kWRho, WPR>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
 }
 
-template <int CPT, int BY>
-__global__ void __launch_bounds__(64 * BY) r_apply(LevelView<double> L, const double* __restrict__ x, double* __restrict__ y,
-                                                  double inv_h2, int kper, int xcd)
+template <int CPT, int BY, int WPR = 1>
+__global__ void __launch_bounds__(64 * WPR * BY) r_apply(LevelView<double> L, const double* __restrict__ x,
+                                                        double* __restrict__ y, double inv_h2, int kper, int xcd)
 {
     OpApply<double> op{x, y, inv_h2};
     double acc[1] = {0.0};
-    march_rw<double, CPT, BY>(L, kper, xcd, op, acc);
+    march_rw<double, CPT, BY, decltype(op), double[1], kWRho, WPR>(L, kper, xcd, op, acc);
 }
 
 // Row-wave passes of a float32 coarse level with stored bfloat16 weights (the

@@ -251,19 +251,31 @@ struct Params {
     int oxcd = 1;               // the same for the overlapped-tile launches (-1: as xcd); their
                                 // ring rows then come from the L2 of the XCD, measured 3 % faster
     bool rho = true;            // finest-level march kernels form the weights from the density
-    bool rw = true;             // row-wave kernels (a wavefront per whole row) for the finest-level float64
-                                // residual and operator when nx is 64, 128, 192 or 256
-    bool rwdir = false;         // ... and for the direction update (measured slower: 435 against 414 us)
-    int rwblocks = 512;         // blocks of a row-wave launch, at most (z split to reach it)
-    int rwrows = 8;             // rows (wavefronts) of a row-wave block: 4 or 8
+    bool rw = true;             // row-wave kernels (whole rows) for the finest-level float64 residual and
+                                // operator when nx is 64, 128, 192 or 256
+    int rwsplit = 2;            // wavefronts per row of those passes where nx is 128 or 256: 1 or 2 (a
+                                // row over two wavefronts holds half the cells per lane: 3-4 waves
+                                // per SIMD instead of 2 for the direction update)
+    int rwdir = 2;              // row-wave direction update: 0 never, 1 always, 2 with split rows (one
+                                // wavefront per row measured slower than the tiles: 415 against 402 us;
+                                // split rows faster: 366 us)
+    int rwblocks = 512;         // blocks of a finest-level row-wave launch, at most (z split to reach it),
+    int rwrows = 8;             // rows per block (4 or 8) and band order, one wavefront per row
+    int rwsblocks = 256;        // the same with split rows (rows 4, 6 or 8), measured best at 256 blocks
+    int rwsrows = 4;            // of 4 rows in the plain band order (366 us; 8 rows 448, 384 blocks 453)
+    int rwsxcd = 0;
+    int rwcrows = 8;            // rows of a coarse-level row-wave block: 4 or 8
+    int rwcblocks = 512;        // blocks of a coarse-level row-wave launch, at most
+    int rwcxcd = 1;             // XCD-aware band order for them
     bool rwc = true;            // row-wave passes on float32 coarse levels with bfloat16 weights (nx 64..256)
     bool rwf = true;            // row-wave forms of the fused float32 finest-level passes (nx 128 or 256)
     int rwfrows = 12;           // their rows per block, ring included: 8, 12 or 16 (12: the most rows whose
                                 // registers (153 per lane) still fit three waves per SIMD)
     int rwfblocks = 256;        // their blocks per launch, at most (one per CU)
     int rwfxcd = 0;             // XCD-aware band order for them (measured slower: 265 against 213 us)
-    int rwxcd = 1;              // XCD-aware band order for the row-wave launches (neighbouring row bands,
-                                // whose halo rows overlap, share an L2)
+    int rwxcd = 1;              // XCD-aware band order for the finest-level row-wave launches with one
+                                // wavefront per row (neighbouring row bands, whose halo rows overlap,
+                                // share an L2)
 };
 
 struct Handle {
@@ -763,7 +775,8 @@ static MGeo march_geo(const Handle* H, const LevelView<T>& v, int bx_max, bool e
 // weights and a row of 64, 128, 192 or 256 cells.
 struct RwGeo {
     dim3 grid, block;
-    int kper = 0, cpt = 0, rows = 8;
+    int kper = 0, cpt = 0, rows = 8, wpr = 1;  // wpr: wavefronts per row
+    int xcd = 0;                               // XCD-aware band order
 };
 // z split of a row-wave launch of gy bands: about max_blocks blocks of kper
 // planes (kper even when the pass pairs planes).  With the XCD-aware band order
@@ -785,16 +798,21 @@ static RwGeo rw_geo(const Handle* H, const LevelView<double>& v)
 {
     RwGeo g;
     if (!H->prm.rw || !H->prm.march || !v.rho || v.nx % 64 != 0 || v.nx > 256) return g;
-    const int rows = H->prm.rwrows;
+    // a row over two wavefronts where the row is 128 or 256 cells
+    const int wpr = (H->prm.rwsplit == 2 && v.nx % 128 == 0) ? 2 : 1;
+    const int rows = wpr == 2 ? H->prm.rwsrows : H->prm.rwrows;
+    const int xcd = wpr == 2 ? H->prm.rwsxcd : H->prm.rwxcd;
     const int gy = (v.ny + rows - 1) / rows;
     int gz, kper;
-    rw_zsplit(H->prm.rwxcd, gy, v.nz, H->prm.rwblocks, false, gz, kper);
+    rw_zsplit(xcd, gy, v.nz, wpr == 2 ? H->prm.rwsblocks : H->prm.rwblocks, false, gz, kper);
     if ((size_t)gy * gz > (size_t)kMaxPartialBlocks) return g;
     g.grid = dim3(1, gy, gz);
-    g.block = dim3(64, rows, 1);
+    g.block = dim3(64 * wpr, rows, 1);
+    g.xcd = xcd;
     g.rows = rows;
     g.kper = kper;
-    g.cpt = v.nx / 64;
+    g.wpr = wpr;
+    g.cpt = v.nx / (64 * wpr);
     return g;
 }
 // Row-wave geometry of a pass on a float32 level with bfloat16 weights, or cpt = 0.
@@ -804,16 +822,17 @@ static RwGeo rwc_geo(const Handle* H, const LevelView<T>& v)
     RwGeo g;
     if constexpr (std::is_same_v<T, float>) {
         if (!H->prm.rwc || !H->prm.march || !v.hwx || v.nx % 64 != 0 || v.nx > 256) return g;
-        const int rows = H->prm.rwrows;
+        const int rows = H->prm.rwcrows;
         const int gy = (v.ny + rows - 1) / rows;
         int gz, kper;
-        rw_zsplit(H->prm.rwxcd, gy, v.nz, H->prm.rwblocks, false, gz, kper);
+        rw_zsplit(H->prm.rwcxcd, gy, v.nz, H->prm.rwcblocks, false, gz, kper);
         if ((size_t)gy * gz > (size_t)kMaxPartialBlocks) return g;
         g.grid = dim3(1, gy, gz);
         g.block = dim3(64, rows, 1);
         g.kper = kper;
         g.cpt = v.nx / 64;
         g.rows = rows;
+        g.xcd = H->prm.rwcxcd;
     }
     return g;
 }
@@ -834,6 +853,25 @@ static void with_cpt(const RwGeo& g, F&& f)
     }
 }
 
+// Calls f(BxC<cpt>{}, BxC<rows>{}, BxC<wpr>{}) for the finest-level float64
+// row-wave instantiations: one wavefront per row as with_cpt, or a row over two
+// wavefronts (cpt 1 or 2, rows 4, 6 or 8).
+template <class F>
+static void with_cpt_rw(const RwGeo& g, F&& f)
+{
+    if (g.wpr == 1) {
+        with_cpt(g, [&](auto C, auto Y) { f(C, Y, BxC<1>{}); });
+        return;
+    }
+    auto rows = [&](auto C) {
+        if (g.rows == 4) f(C, BxC<4>{}, BxC<2>{});
+        else if (g.rows == 6) f(C, BxC<6>{}, BxC<2>{});
+        else f(C, BxC<8>{}, BxC<2>{});
+    };
+    if (g.cpt == 1) rows(BxC<1>{});
+    else rows(BxC<2>{});
+}
+
 // Launchers: the plane-march kernels, or the per-column kernels when the march is off.
 
 template <class T>
@@ -845,7 +883,7 @@ static void launch_first(Handle* H, const LevelView<T>& v, const T* f, T* x)
         if (rg.cpt) {
             with_cpt(rg, [&](auto C, auto Y) {
                 r_smooth_first<decltype(C)::value, decltype(Y)::value>
-                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, rg.kper, H->prm.rwxcd, om);
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, rg.kper, rg.xcd, om);
             });
             check_launch();
             return;
@@ -877,7 +915,7 @@ static dim3 launch_half(Handle* H, const LevelView<T>& v, const T* f, T* x, int 
         if (rg.cpt) {
             with_cpt(rg, [&](auto C, auto Y) {
                 r_smooth_half<decltype(C)::value, decltype(Y)::value, NDOT, TQ>
-                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, colour, rg.kper, H->prm.rwxcd, q, R, om);
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, colour, rg.kper, rg.xcd, q, R, om);
             });
             check_launch();
             return rg.grid;
@@ -1013,7 +1051,7 @@ static void launch_prolong_black(Handle* H, const LevelView<T>& v, const T* f, c
         if (rg.cpt) {
             with_cpt(rg, [&](auto C, auto Y) {
                 r_prolong_black<decltype(C)::value, decltype(Y)::value>
-                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, e, wc, y, rg.kper, H->prm.rwxcd, om);
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, f, x, e, wc, y, rg.kper, rg.xcd, om);
             });
             check_launch();
             return;
@@ -1046,26 +1084,27 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
                 constexpr int CPT = decltype(C)::value, BY = decltype(Y)::value;
                 if (use_beta)
                     r_dir_apply_f32<CPT, BY, true><<<rg.grid, rg.block, 0, H->stream>>>(
-                        v, z, dold, dnew, q, r, beta, mean, use_mean, rg.kper, H->prm.rwxcd, R);
+                        v, z, dold, dnew, q, r, beta, mean, use_mean, rg.kper, rg.xcd, R);
                 else
                     r_dir_apply_f32<CPT, BY, false><<<rg.grid, rg.block, 0, H->stream>>>(
-                        v, z, dold, dnew, q, r, beta, mean, use_mean, rg.kper, H->prm.rwxcd, R);
+                        v, z, dold, dnew, q, r, beta, mean, use_mean, rg.kper, rg.xcd, R);
             });
             check_launch();
             return rg.grid;
         }
     }
     if constexpr (FINE && std::is_same_v<T, double>) {
-        const RwGeo rg = H->prm.rwdir ? rw_geo(H, v) : RwGeo{};
+        RwGeo rg = H->prm.rwdir ? rw_geo(H, v) : RwGeo{};
+        if (H->prm.rwdir == 2 && rg.wpr == 1) rg.cpt = 0;  // one wavefront per row: the tiles are faster
         if (rg.cpt) {
-            with_cpt(rg, [&](auto C, auto Y) {
-                constexpr int CPT = decltype(C)::value, BY = decltype(Y)::value;
+            with_cpt_rw(rg, [&](auto C, auto Y, auto P) {
+                constexpr int CPT = decltype(C)::value, BY = decltype(Y)::value, WPR = decltype(P)::value;
                 if (use_beta)
-                    r_dir_apply<CPT, BY, TZ, true, FINE><<<rg.grid, rg.block, 0, H->stream>>>(
-                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, rg.kper, H->prm.rwxcd, R);
+                    r_dir_apply<CPT, BY, TZ, true, FINE, WPR><<<rg.grid, rg.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, rg.kper, rg.xcd, R);
                 else
-                    r_dir_apply<CPT, BY, TZ, false, FINE><<<rg.grid, rg.block, 0, H->stream>>>(
-                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, rg.kper, H->prm.rwxcd, R);
+                    r_dir_apply<CPT, BY, TZ, false, FINE, WPR><<<rg.grid, rg.block, 0, H->stream>>>(
+                        v, z, dold, dnew, q, r, x, beta, mean, use_mean, aprev, rg.kper, rg.xcd, R);
             });
             check_launch();
             return rg.grid;
@@ -1528,9 +1567,9 @@ static double true_residual(Handle* H, const double* x, double* xc, float* r32)
         const Reduce R = red(H, G_TRR, G_TRSUM);
         const RwGeo rg = rw_geo(H, v);
         if (rg.cpt) {
-            with_cpt(rg, [&](auto C, auto Y) {
-                r_true_residual<decltype(C)::value, decltype(Y)::value>
-                    <<<rg.grid, rg.block, 0, H->stream>>>(v, H->f64, x, H->r64, rg.kper, H->prm.rwxcd, R, xc, r32);
+            with_cpt_rw(rg, [&](auto C, auto Y, auto P) {
+                r_true_residual<decltype(C)::value, decltype(Y)::value, decltype(P)::value>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, H->f64, x, H->r64, rg.kper, rg.xcd, R, xc, r32);
             });
             grid = rg.grid;
         } else if (H->prm.march) {
@@ -1667,10 +1706,17 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_FBLOCKS")) p.fblocks = std::max(32, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_MBLOCKS")) p.mblocks = std::max(64, std::min(kMaxRedBlocks, atoi(s)));
     if (const char* s = getenv("PP_RW")) p.rw = atoi(s) != 0;
-    if (const char* s = getenv("PP_RWDIR")) p.rwdir = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWDIR")) p.rwdir = std::max(0, std::min(2, atoi(s)));
     if (const char* s = getenv("PP_RWBLOCKS")) p.rwblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWXCD")) p.rwxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWROWS")) p.rwrows = atoi(s) <= 4 ? 4 : 8;
+    if (const char* s = getenv("PP_RWSPLIT")) p.rwsplit = atoi(s) == 2 ? 2 : 1;
+    if (const char* s = getenv("PP_RWSROWS")) p.rwsrows = atoi(s) <= 4 ? 4 : (atoi(s) <= 6 ? 6 : 8);
+    if (const char* s = getenv("PP_RWSBLOCKS")) p.rwsblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
+    if (const char* s = getenv("PP_RWSXCD")) p.rwsxcd = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWCROWS")) p.rwcrows = atoi(s) <= 4 ? 4 : 8;
+    if (const char* s = getenv("PP_RWCBLOCKS")) p.rwcblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
+    if (const char* s = getenv("PP_RWCXCD")) p.rwcxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
     if (const char* s = getenv("PP_RWC")) p.rwc = atoi(s) != 0;
     if (const char* s = getenv("PP_RWFXCD")) p.rwfxcd = atoi(s) != 0;
@@ -1934,9 +1980,9 @@ int pp_apply(pp_handle h, const double* x, double* y)
         if (rg.cpt) {
             // the finest-level operator exactly as the solve's passes form it
             const LevelView<double> v = fine64(H);
-            with_cpt(rg, [&](auto C, auto Y) {
-                r_apply<decltype(C)::value, decltype(Y)::value>
-                    <<<rg.grid, rg.block, 0, H->stream>>>(v, x, y, inv_h2, rg.kper, H->prm.rwxcd);
+            with_cpt_rw(rg, [&](auto C, auto Y, auto P) {
+                r_apply<decltype(C)::value, decltype(Y)::value, decltype(P)::value>
+                    <<<rg.grid, rg.block, 0, H->stream>>>(v, x, y, inv_h2, rg.kper, rg.xcd);
             });
         } else if (H->prm.march) {
             const LevelView<double> v = fine64(H);
