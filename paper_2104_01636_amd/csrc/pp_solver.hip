@@ -264,6 +264,8 @@ struct Params {
     int rwsblocks = 256;        // the same with split rows (rows 4, 6 or 8), measured best at 256 blocks
     int rwsrows = 4;            // of 4 rows in the plain band order (366 us; 8 rows 448, 384 blocks 453)
     int rwsxcd = 0;
+    int eblocks = 512;          // blocks of the finest-level r/q update, at most (164 us with 512, 185
+                                // with 2048, 215 with 256)
     int rwcrows = 8;            // rows of a coarse-level row-wave block: 4 or 8
     int rwcblocks = 512;        // blocks of a coarse-level row-wave launch, at most
     int rwcxcd = 1;             // XCD-aware band order for them
@@ -1351,6 +1353,16 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l)
     return V.xk;
 }
 
+// Grid of the finest-level r/q (and x) update (a grid-stride loop over element
+// pairs): at most eblocks blocks (at most kMaxPartialBlocks, the partials a
+// reduction can hold).  The one-element-per-step passes keep lin_grid (fewer
+// blocks made them slower: the density 110 -> 187 us with 512).
+static dim3 fine_grid(const Handle* H, size_t n)
+{
+    const size_t b = (n / 2 + kBlock - 1) / kBlock;
+    return dim3((unsigned)std::max<size_t>(1, std::min<size_t>(b, (size_t)H->prm.eblocks)));
+}
+
 // One step of the finest-level flexible CG, float64 throughout (x, r, d, q and
 // the operator from rho), preconditioned by one multigrid cycle in precision P:
 // z = M r (the cycle also reduces sum(z) and <z, q_old>), d = (z - mean z) +
@@ -1388,12 +1400,12 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
         {
             // reads r and q; writes r and the float32 copy of r
             TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (24.0 + (H->r32 ? 4.0 : 0.0)));
-            k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
-                                                                        coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1, R,
-                                                                        H->r32, 0);
+            k_update_xr<double><<<fine_grid(H, n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
+                                                                          coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1, R,
+                                                                          H->r32, 0);
             check_launch();
         }
-        finish(H, R, lin_grid(n0), 2);
+        finish(H, R, fine_grid(H, n0), 2);
     }
     std::swap(H->d, H->d2);
 }
@@ -1465,7 +1477,7 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
         const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
         const int last = k - 1;
         const Coefs a = coef(H, lslot(0, S_DR), lslot(0, (last & 1) ? S_DQ1 : S_DQ0), 1.0);
-        k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d, H->r64, H->q64, a, 0, 1, 0,
+        k_update_xr<double><<<fine_grid(H, n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d, H->r64, H->q64, a, 0, 1, 0,
                                                                     red(H, G_FN2), (float*)nullptr, 1);
         check_launch();
     }
@@ -1633,7 +1645,7 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
             if (H->prm.mg_solver) {
                 // the paper's form: multigrid cycles with red-black SOR as the solver, x += M (f - K x)
                 double* z = mgcycle<double, double>(H, H->h64, 0, H->r64, 0, nullptr);
-                k_update_xr<double><<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, H->x64, z, H->r64, H->q64,
+                k_update_xr<double><<<fine_grid(H, n0), kBlock, 0, H->stream>>>((int)n0, H->x64, z, H->r64, H->q64,
                                                                             coef(H, G_ONE, -1, 1.0), 0, 1, 0,
                                                                             red(H, G_FN2), (float*)nullptr, 1);
                 check_launch();
@@ -1715,6 +1727,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_RWSBLOCKS")) p.rwsblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWSXCD")) p.rwsxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWCROWS")) p.rwcrows = atoi(s) <= 4 ? 4 : 8;
+    if (const char* s = getenv("PP_EBLOCKS")) p.eblocks = std::max(64, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWCBLOCKS")) p.rwcblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWCXCD")) p.rwcxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
