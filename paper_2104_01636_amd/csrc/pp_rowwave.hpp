@@ -1,11 +1,15 @@
-// pp_rowwave.hpp -- row-wave plane-marching kernels for the finest level (gfx950).
+// pp_rowwave.hpp -- row-wave plane-marching kernels (gfx950): the finest
+// level's float64 passes and the passes of the coarse float32 levels with
+// bfloat16 weights.
 //
 // The same operations as the march kernels of pp_march.hpp, laid out so that a
 // wavefront covers one whole grid row: the level's x extent is 64 * CPT cells
-// and lane l owns the CPT consecutive cells 64-aligned at l * CPT.  A block of
-// 64 x BY threads is BY rows (one per wavefront) and walks a range of z planes.
+// and lane l owns the CPT consecutive cells at l * CPT.  A block of 64 x BY
+// threads is BY rows (one per wavefront) and walks a range of z planes.  (On
+// the finest level a row of 128 or 256 cells can instead be split over WPR = 2
+// wavefronts, a block of 64 WPR x BY threads; see march_rw.)
 //   * x neighbours are in the lane's own registers or in the next / previous
-//     lane (wavefront shuffles); the walls at i = 0 and i = nx-1 bound every
+//     lane (wavefront shifts); the walls at i = 0 and i = nx-1 bound every
 //     row, so there is no x halo at all (on a tiled row every tile edge would
 //     fetch a whole cache line for one element per array and plane);
 //   * y neighbours of the block's inner rows come from a double-buffered LDS
@@ -266,9 +270,6 @@ __device__ inline void march_rw(const LevelView<T>& L, int kper, int xcd, Op& op
     }
     if (k < k1) step(R[0], R[1], k, (k - k0) & 1);
 }
-
-// Rows (wavefronts) of a row-wave block: 4 or 8.
-constexpr int kRwRowsMax = 8;
 
 // Row-wave variants of the finest-level float64 passes of the Krylov step
 // (same operations and reductions as m_dir_apply, m_true_residual, m_apply).
