@@ -407,14 +407,14 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(int n, const T* __restri
 
 // ---------------------------------------------------------------- float64 outer pieces
 
-// r = f - K x in float64; reduces ||r||^2 and sum(r); xc (or null) receives a
-// copy of x, r32 (or null) the float32 copy of r.
+// r = f - K x in float64; reduces ||r||^2, sum(r) and sum(x); xc (or null)
+// receives a copy of x, r32 (or null) the float32 copy of r.
 __global__ void __launch_bounds__(kBlock) k_true_residual(LevelView<double> L, const double* __restrict__ f,
                                                          const double* __restrict__ x, double* __restrict__ r, int kper,
                                                          Reduce R, double* __restrict__ xc, float* __restrict__ r32)
 {
     Tile t = tile(L.nx, L.ny, L.nz, kper);
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     if (t.act) {
         for (int k = t.k0; k < t.k1; ++k) {
             const int c = cell(L.nx, L.ny, t.i, t.j, k);
@@ -426,9 +426,10 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(LevelView<double> L, c
             if (r32) r32[c] = (float)rv;
             acc[0] += rv * rv;
             acc[1] += rv;
+            acc[2] += x[c];
         }
     }
-    reduce_finish<2>(acc, R);
+    reduce_finish<3>(acc, R);
 }
 
 // Reduces sum(x) over finite entries and the count of non-finite entries (and
@@ -520,6 +521,33 @@ __global__ void __launch_bounds__(kBlock) k_fine_diag(int nx, int ny, int nz, co
         const double inv = 1.0 / d;
         if (invd64) invd64[c] = inv;
         if (invd32) invd32[c] = (float)inv;
+    }
+}
+
+// The float32 1/D of the finest level for the float32 cycle, from the float32
+// density, with the weights formed as its passes form them (2 / (rho_L + rho_R)
+// by the hardware reciprocal), added in nbsum's order: the diagonal the float32
+// passes' own weights imply (a float64 1/D would cost seven float64 divisions a
+// cell for a value rounded to float32).
+__global__ void __launch_bounds__(kBlock) k_fine_diag32(int nx, int ny, int nz, const float* __restrict__ rho,
+                                                       float* __restrict__ invd32, int kper)
+{
+    Tile t = tile(nx, ny, nz, kper);
+    if (!t.act) return;
+    const int sy = nx, sz = nx * ny;
+    auto beta = [](float a, float b) { return 2.0f * __builtin_amdgcn_rcpf(a + b); };
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int c = cell(nx, ny, t.i, t.j, k);
+        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz, ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
+        const float r = rho[c];
+        float d = 0.0f;
+        if (t.i > 0) d += beta(rho[c - 1], r);
+        if (t.i < nx - 1) d += beta(r, rho[c + 1]);
+        if (t.j > 0) d += beta(rho[c - sy], r);
+        if (t.j < ny - 1) d += beta(r, rho[c + sy]);
+        d += beta(rho[cb], r);
+        d += beta(r, rho[ct]);
+        invd32[c] = __builtin_amdgcn_rcpf(d);
     }
 }
 

@@ -382,7 +382,7 @@ struct OpDir {
 };
 
 template <class T>
-struct OpResidual {  // r = f - K x; dots ||r||^2, sum r; optionally a copy of x and a float32 copy of r
+struct OpResidual {  // r = f - K x; sums ||r||^2, sum r, sum x; optionally a copy of x and a float32 copy of r
     const T* f;
     const T* x;
     T* r;
@@ -403,6 +403,7 @@ struct OpResidual {  // r = f - K x; dots ||r||^2, sum r; optionally a copy of x
         if (r32) r32[c] = (float)rv;
         acc[0] += (double)rv * (double)rv;
         acc[1] += (double)rv;
+        acc[2] += (double)vc;
     }
 };
 
@@ -724,9 +725,9 @@ __global__ void __launch_bounds__((kMarchThreads<double, WM == kWRho>)) m_true_r
                                                          Reduce R, double* __restrict__ xc, float* __restrict__ r32)
 {
     OpResidual<double> op{f, x, r, xc, r32};
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     march<double, BX, WM>(L, kper, xcd, op, acc);
-    reduce_finish<2>(acc, R);
+    reduce_finish<3>(acc, R);
 }
 
 }  // namespace pp

@@ -294,9 +294,9 @@ __global__ void __launch_bounds__(64 * WPR * BY) r_true_residual(LevelView<doubl
                                                           float* __restrict__ r32)
 {
     OpResidual<double> op{f, x, r, xc, r32};
-    double acc[2] = {0.0, 0.0};
-    march_rw<double, CPT, BY, decltype(op), double[2], kWRho, WPR>(L, kper, xcd, op, acc);
-    reduce_finish<2>(acc, R);
+    double acc[3] = {0.0, 0.0, 0.0};
+    march_rw<double, CPT, BY, decltype(op), double[3], kWRho, WPR>(L, kper, xcd, op, acc);
+    reduce_finish<3>(acc, R);
 }
 
 template <int CPT, int BY, int WPR = 1>

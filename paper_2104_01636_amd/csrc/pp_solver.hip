@@ -648,9 +648,9 @@ static Reduce red(Handle* H, int s0, int s1 = 0, int s2 = 0, int s3 = 0)
 }
 // The same for totals the host reads next: the finishing kernel also writes
 // them into the mapped host slots (see fetch_slots).
-static Reduce red_host(Handle* H, int s0, int s1 = 0)
+static Reduce red_host(Handle* H, int s0, int s1 = 0, int s2 = 0)
 {
-    Reduce R = red(H, s0, s1);
+    Reduce R = red(H, s0, s1, s2);
     R.host = H->host_slots_dev;
     return R;
 }
@@ -1508,9 +1508,14 @@ static void set_density(Handle* H, const double* rho)
     for (int l = 0; l < nl; ++l) {
         Geo g = geo(H->lnx[l], H->lny[l], H->lnz[l]);
         if (l == 0 && fine_rho) {
-            // no stored finest weights: 1/D from the density
-            k_fine_diag<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, H->rho64, H->c64[0].invd,
-                                                           H->c32[0].invd, g.kper);
+            // no stored finest weights: 1/D from the density (float64 for the float64 cycle, float32
+            // as the float32 passes form their weights for the float32 cycle)
+            if (H->c64[0].invd)
+                k_fine_diag<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, H->rho64, H->c64[0].invd,
+                                                               H->c32[0].invd, g.kper);
+            else
+                k_fine_diag32<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, H->rho32, H->c32[0].invd,
+                                                                 g.kper);
             check_launch();
             continue;
         }
@@ -1564,8 +1569,8 @@ static double prepare_rhs(Handle* H, const double* rhs)
     return std::sqrt(H->host_slots[G_FN2]);
 }
 
-// r64 = f64 - K x in float64; returns ||r|| (sum(r) in slot G_TRSUM).  xc (or
-// null) receives a copy of x, r32 (or null) the float32 copy of r.
+// r64 = f64 - K x in float64; returns ||r|| (sum(r) in slot G_TRSUM, sum(x) in
+// G_XSUM).  xc (or null) receives a copy of x, r32 (or null) the float32 copy of r.
 static double true_residual(Handle* H, const double* x, double* xc, float* r32)
 {
     const pp_config& cfg = H->cfg;
@@ -1576,7 +1581,7 @@ static double true_residual(Handle* H, const double* x, double* xc, float* r32)
         TimeScope ts(H, kid<double>(KT_TRUE_RESIDUAL),
                      (double)cfg.nx * cfg.ny * cfg.nz *
                          (24.0 + 8.0 * weight_arrays(H, v) + (xc ? 8.0 : 0.0) + (r32 ? 4.0 : 0.0)));
-        const Reduce R = red(H, G_TRR, G_TRSUM);
+        const Reduce R = red(H, G_TRR, G_TRSUM, G_XSUM);
         const RwGeo rg = rw_geo(H, v);
         if (rg.cpt) {
             with_cpt_rw(rg, [&](auto C, auto Y, auto P) {
@@ -1600,18 +1605,15 @@ static double true_residual(Handle* H, const double* x, double* xc, float* r32)
         }
         check_launch();
     }
-    finish(H, red_host(H, G_TRR, G_TRSUM), grid, 2);
+    finish(H, red_host(H, G_TRR, G_TRSUM, G_XSUM), grid, 3);
     fetch_slots(H, G_TRR, 2);
     return std::sqrt(std::max(0.0, H->host_slots[G_TRR]));
 }
 
-// out = x - mean(x) (out may be x)
+// out = x - mean(x), with sum(x) already in slot G_XSUM (the last true_residual of x)
 static void remove_mean(Handle* H, const double* x, double* out)
 {
     const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
-    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, 0, red(H, G_XSUM, G_XBAD));
-    check_launch();
-    finish(H, red(H, G_XSUM, G_XBAD), lin_grid(n0), 2);
     k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, x, out, 1.0, coef(H, G_XSUM, -1, 1.0 / (double)n0), 0,
                                                           red(H, G_FN2));
     check_launch();
@@ -1656,10 +1658,9 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
             else iters += fcg(H, H->h32, cfg.tol * fn, max_it - iters, nullptr);
             ++restarts;  // the recursion's residual met the tolerance: check the true one
         }
-        // p = x - mean(x), and the final float64 residual of p
+        // every exit from the loop follows a true residual of x: p = x - mean(x) with its sum of
+        // x, and that residual is p's (K 1 = 0: the shift changes it only by rounding)
         remove_mean(H, H->x64, p);
-        rel = true_residual(H, p, nullptr, nullptr) / fn;
-        converged = converged || rel <= cfg.tol;
     }
     PP_HIP(hipStreamSynchronize(H->stream));
     auto t1 = std::chrono::steady_clock::now();
