@@ -298,6 +298,29 @@ struct OpFirst {  // red-black SOR from a zero guess (red omega f/D, black one u
     }
 };
 
+// OpFirst on the K-cycle residual of the next step, f = r - alpha q (formed as
+// the separate update forms it), which the pass also stores into fo (not r: the
+// neighbouring blocks still read r).
+template <class T>
+struct OpFirstR {
+    const T *r, *q, *invd;
+    T* fo;
+    T* x;
+    T alpha, omega;
+    struct Raw { T f, invd; };
+    using Ex = None;
+    __device__ Raw load(int c, int, int, int) const { return {r[c] - alpha * q[c], invd[c]}; }
+    __device__ T val(const Raw& a) const { return omega * (a.f * a.invd); }
+    __device__ Ex extra(int) const { return {}; }
+    template <class A>
+    __device__ void apply(int c, int i, int j, int k, T vc, const Raw& a, const Ex&, const Stencil<T>& st, A&, bool act) const
+    {
+        if (!act) return;
+        fo[c] = a.f;
+        x[c] = (((i + j + k) & 1) == 0) ? vc : omega * ((st.s + a.f) * a.invd);
+    }
+};
+
 template <class T, int NDOT, class TQ>
 struct OpHalf {  // one colour of a red-black SOR sweep in place; optional dots
     const T* f;
@@ -351,9 +374,10 @@ struct OpProlongBlack {  // y = x + wc P e on red cells; black SOR update from t
 };
 
 // d_new = (z - m) + b d_old (d_new = z - m without BETA), q = K d_new; dots
-// <d,q> and <d,r>.  FINE (the finest level's Krylov step): with BETA also the
-// previous step's deferred x += ap * d_old.
-template <class T, class TZ, bool BETA, bool FINE>
+// <d,q> and <d,r>.  With BETA also the previous step's deferred update of x:
+// XU 2 x += ap * d_old (the finest level's Krylov step, FINE), XU 1 x = ap * d_old
+// (the second step of a K-cycle whose x starts at zero), XU 0 none.
+template <class T, class TZ, bool BETA, bool FINE, int XU = FINE ? 2 : 0>
 struct OpDir {
     const TZ* z;
     const T* dold;
@@ -366,7 +390,7 @@ struct OpDir {
     struct Ex { T r, x; };
     __device__ Raw load(int c, int, int, int) const { return {z[c], BETA ? dold[c] : T(0)}; }
     __device__ T val(const Raw& a) const { return BETA ? ((T)a.z - m) + b * a.d : ((T)a.z - m); }
-    __device__ Ex extra(int c) const { return {r[c], (FINE && BETA) ? x[c] : T(0)}; }
+    __device__ Ex extra(int c) const { return {r[c], (XU == 2 && BETA) ? x[c] : T(0)}; }
     template <class A>
     __device__ void apply(int c, int, int, int, T vc, const Raw& own, const Ex& ev, const Stencil<T>& st, A& acc,
                           bool act) const
@@ -377,7 +401,8 @@ struct OpDir {
         q[c] = qc;
         acc[0] += (double)vc * (double)qc;
         acc[1] += (double)vc * (double)ev.r;
-        if constexpr (FINE && BETA) x[c] = ev.x + ap * own.d;
+        if constexpr (XU == 2 && BETA) x[c] = ev.x + ap * own.d;
+        if constexpr (XU == 1 && BETA) x[c] = ap * own.d;
     }
 };
 

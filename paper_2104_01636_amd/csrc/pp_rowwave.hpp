@@ -341,17 +341,33 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_black(LevelView<float> L, c
     march_rw<float, CPT, BY, OpProlongBlack<float>, double[1], kWHalf>(L, kper, xcd, op, acc);
 }
 
-template <int CPT, int BY, bool BETA>
+// XU: the K-cycle's deferred update of x (see OpDir), with coefficient aprev.
+template <int CPT, int BY, bool BETA, int XU = 0>
 __global__ void __launch_bounds__(64 * BY) r_dir_apply_f32(LevelView<float> L, const float* __restrict__ z,
                                                           const float* __restrict__ dold, float* __restrict__ dnew,
                                                           float* __restrict__ q, const float* __restrict__ r, Coefs beta,
-                                                          Coefs mean, int use_mean, int kper, int xcd, Reduce R)
+                                                          Coefs mean, int use_mean, int kper, int xcd, Reduce R,
+                                                          float* __restrict__ x = nullptr, Coefs aprev = Coefs{})
 {
-    OpDir<float, float, BETA, false> op{z, dold, r, dnew, q, nullptr, BETA ? (float)beta.get() : 0.0f,
-                                        use_mean ? (float)mean.get() : 0.0f, 0.0f};
+    using Op = OpDir<float, float, BETA, false, XU>;
+    Op op{z, dold, r, dnew, q, x, BETA ? (float)beta.get() : 0.0f, use_mean ? (float)mean.get() : 0.0f,
+          (BETA && XU > 0) ? (float)aprev.get() : 0.0f};
     double acc[2] = {0.0, 0.0};
-    march_rw<float, CPT, BY, OpDir<float, float, BETA, false>, double[2], kWHalf>(L, kper, xcd, op, acc);
+    march_rw<float, CPT, BY, Op, double[2], kWHalf>(L, kper, xcd, op, acc);
     reduce_finish<2>(acc, R);
+}
+
+// The first sweep from zero of a K-cycle step on the step's residual r - alpha q
+// of the previous step's r and q, which it also stores into fo.
+template <int CPT, int BY>
+__global__ void __launch_bounds__(64 * BY) r_smooth_first_r(LevelView<float> L, const float* __restrict__ r,
+                                                           const float* __restrict__ q, Coefs alpha,
+                                                           float* __restrict__ fo, float* __restrict__ x, int kper,
+                                                           int xcd, float omega)
+{
+    OpFirstR<float> op{r, q, L.invd, fo, x, (float)alpha.get(), omega};
+    double acc[1] = {0.0};
+    march_rw<float, CPT, BY, OpFirstR<float>, double[1], kWHalf>(L, kper, xcd, op, acc);
 }
 
 }  // namespace pp

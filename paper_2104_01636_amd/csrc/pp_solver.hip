@@ -189,6 +189,7 @@ struct Lev {
     bool kcyc;            // solved by K-cycle steps
     T *rhs = nullptr, *c = nullptr, *c2 = nullptr;
     T *xk = nullptr, *d = nullptr, *d2 = nullptr, *q = nullptr;  // Krylov levels
+    T* rhs2 = nullptr;                 // K-cycle: the other residual buffer (float32 levels)
     T *d_a = nullptr, *d_b = nullptr;  // the two search-direction buffers (d, d2 alternate between them)
     T *w1 = nullptr, *rr = nullptr;    // W-cycle: the first visit's correction, the coarse residual
 };
@@ -266,6 +267,9 @@ struct Params {
     int rwsxcd = 0;
     int eblocks = 512;          // blocks of the finest-level r/q update, at most (164 us with 512, 185
                                 // with 2048, 215 with 256)
+    bool kfold = true;          // K-cycle steps on row-wave float32 levels without a separate x/r update:
+                                // r -= alpha q rides on the next step's first sweep, x += alpha d on
+                                // the next step's direction update
     int rwcrows = 8;            // rows of a coarse-level row-wave block: 4 or 8
     int rwcblocks = 512;        // blocks of a coarse-level row-wave launch, at most
     int rwcxcd = 1;             // XCD-aware band order for them
@@ -552,6 +556,7 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
                 V.rr = P.template take<T>(V.n);
             }
             if (V.kcyc) {
+                if constexpr (std::is_same_v<T, float>) V.rhs2 = P.template take<T>(V.n);
                 V.xk = P.template take<T>(V.n);
                 V.d = V.d_a = P.template take<T>(V.n);
                 V.d2 = V.d_b = P.template take<T>(V.n);
@@ -1170,14 +1175,43 @@ static int sweeps_of(const Handle* H, const Lev<T>& V, int l)
                                                               : H->prm.nuc;
 }
 
+// A K-cycle step's residual formed inside its cycle's first pass: f = r - alpha q
+// from the previous step's r and q, stored into out (see kcycle).
+template <class T>
+struct Fold {
+    const T* r;
+    const T* q;
+    T* out;
+    Coefs alpha;
+};
+
+// The first sweep from zero on fd's residual (row-wave float32 levels: see kfold_ok).
+template <class T>
+static void launch_first_fold(Handle* H, const LevelView<T>& v, const Fold<T>& fd, T* x)
+{
+    if constexpr (std::is_same_v<T, float>) {
+        const RwGeo rg = rwc_geo(H, v);
+        if (rg.cpt) {
+            with_cpt(rg, [&](auto C, auto Y) {
+                r_smooth_first_r<decltype(C)::value, decltype(Y)::value><<<rg.grid, rg.block, 0, H->stream>>>(
+                    v, fd.r, fd.q, fd.alpha, fd.out, x, rg.kper, rg.xcd, (float)H->prm.omega);
+            });
+            check_launch();
+            return;
+        }
+    }
+    throw Fail(PP_ERR_INVALID, "folded K-cycle step on a level without row-wave passes");
+}
+
 // Down leg of a cycle at level l: nu red-black sweeps of K x = f from a zero
 // guess into x, then the residual f - K x summed over the 8 children of each
-// coarse cell into rc (one overlapped-tile launch on a fused level).
+// coarse cell into rc (one overlapped-tile launch on a fused level).  With fold
+// the first sweep forms f itself (f == fold->out).
 template <class T>
-static void cycle_pre(Handle* H, Lev<T>& V, int l, int nu, const T* f, T* x, T* rc)
+static void cycle_pre(Handle* H, Lev<T>& V, int l, int nu, const T* f, T* x, T* rc, const Fold<T>* fold = nullptr)
 {
     const bool fine = (l == 0);
-    if (nu == 1 && fused(H, sizeof(T), V.n)) {
+    if (!fold && nu == 1 && fused(H, sizeof(T), V.n)) {
         // reads f, 1/D and the weights (or the density); writes x and the coarse right-hand side
         TimeScope ts(H, fine ? kid<T>(KT_FIRST_RESTRICT) : -1, (double)V.n * sizeof(T) * (3.125 + weight_arrays(H, V.v)));
         launch_first_restrict<T>(H, V.v, f, x, rc);
@@ -1186,7 +1220,8 @@ static void cycle_pre(Handle* H, Lev<T>& V, int l, int nu, const T* f, T* x, T* 
     {
         // reads f, 1/D and the weights (or the density); writes x
         TimeScope ts(H, fine ? kid<T>(KT_SMOOTH_FIRST) : -1, (double)V.n * sizeof(T) * (3.0 + weight_arrays(H, V.v)));
-        launch_first<T>(H, V.v, f, x);
+        if (fold) launch_first_fold<T>(H, V.v, *fold, x);  // f is fold->out, which this pass writes
+        else launch_first<T>(H, V.v, f, x);
     }
     for (int s = 1; s < nu; ++s) {
         smooth_half(H, V, fine, f, x, 0, 0, (const T*)nullptr, l);
@@ -1241,7 +1276,7 @@ static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x
 // the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, reduced on the last
 // half-sweep into level l's slots.
 template <class T, class TQ = T>
-static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ* q)
+static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ* q, const Fold<T>* fold = nullptr)
 {
     Lev<T>& V = Hh.L[l];
     const bool fine = (l == 0);
@@ -1277,7 +1312,7 @@ static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ*
     }
     const int nu = sweeps_of(H, V, l);
     Lev<T>& C = Hh.L[l + 1];
-    cycle_pre(H, V, l, nu, f, V.c, C.rhs);
+    cycle_pre(H, V, l, nu, f, V.c, C.rhs, fold);
     T* e;
     T wc;
     if (C.kcyc) {
@@ -1335,6 +1370,48 @@ static void update_xr(Handle* H, Lev<T>& V, T* x, int it, int l, bool first, boo
     if (want) finish(H, R, lin_grid(V.n), 2);
 }
 
+// Whether the K-cycle at level V runs without separate x/r updates: a float32
+// level with row-wave passes whose cycle starts with the plain first sweep.
+template <class T>
+static bool kfold_ok(const Handle* H, const Lev<T>& V, int l)
+{
+    if constexpr (std::is_same_v<T, float>) {
+        if (!H->prm.kfold || !V.rhs2 || !rwc_geo(H, V.v).cpt) return false;
+        return !(sweeps_of(H, V, l) == 1 && fused(H, sizeof(T), V.n));
+    }
+    return false;
+}
+
+// Direction update of K-cycle step it on residual r with the previous step's
+// deferred x update (x = alpha d_old at it = 1, x += alpha d_old after).
+template <class T>
+static void dir_apply_fold(Handle* H, Lev<T>& V, const T* z, const T* r, int it, int l)
+{
+    if constexpr (std::is_same_v<T, float>) {
+        const int dq_prev = lslot(l, (it & 1) ? S_DQ0 : S_DQ1);
+        const int dq_cur = lslot(l, (it & 1) ? S_DQ1 : S_DQ0);
+        const Coefs beta = coef(H, lslot(l, S_ZQ), dq_prev, -1.0);
+        const Coefs mn = coef(H, lslot(l, S_SUMZ), -1, 1.0 / (double)V.n);
+        const Coefs aprev = coef(H, lslot(l, S_DR), dq_prev, 1.0);  // read before this launch's totals
+        const Reduce R = red(H, dq_cur, lslot(l, S_DR));
+        const RwGeo rg = rwc_geo(H, V.v);
+        with_cpt(rg, [&](auto C, auto Y) {
+            constexpr int CPT = decltype(C)::value, BY = decltype(Y)::value;
+            if (it == 0)
+                r_dir_apply_f32<CPT, BY, false, 0><<<rg.grid, rg.block, 0, H->stream>>>(
+                    V.v, z, V.d, V.d2, V.q, r, beta, mn, 0, rg.kper, rg.xcd, R, V.xk, aprev);
+            else if (it == 1)
+                r_dir_apply_f32<CPT, BY, true, 1><<<rg.grid, rg.block, 0, H->stream>>>(
+                    V.v, z, V.d, V.d2, V.q, r, beta, mn, 0, rg.kper, rg.xcd, R, V.xk, aprev);
+            else
+                r_dir_apply_f32<CPT, BY, true, 2><<<rg.grid, rg.block, 0, H->stream>>>(
+                    V.v, z, V.d, V.d2, V.q, r, beta, mn, 0, rg.kper, rg.xcd, R, V.xk, aprev);
+        });
+        check_launch();
+        finish(H, R, rg.grid, 2);
+    }
+}
+
 // K-cycle: kit flexible-CG steps on K_l x = rhs_l (rhs_l is used as the residual).
 template <class T>
 static T* kcycle(Handle* H, Hier<T>& Hh, int l)
@@ -1344,6 +1421,35 @@ static T* kcycle(Handle* H, Hier<T>& Hh, int l)
     const int kit = (deepest && (long)V.n > H->prm.kbig && H->prm.kit2 > 0) ? H->prm.kit2 : H->prm.kit;
     V.d = V.d_a;
     V.d2 = V.d_b;
+    if (kfold_ok(H, V, l)) {
+        // the same steps without the separate x/r update launches: step it > 0's cycle forms its
+        // residual r - alpha q of the previous step in its first pass (into the other residual
+        // buffer), its direction update applies the previous step's x update, and the last
+        // step's x update follows the loop
+        const T* r = V.rhs;
+        T* r_other = V.rhs2;
+        for (int it = 0; it < kit; ++it) {
+            T* z;
+            if (it == 0) {
+                z = mgcycle(H, Hh, l, r, 0, V.q);
+            } else {
+                const int dq_prev = lslot(l, ((it - 1) & 1) ? S_DQ1 : S_DQ0);
+                const Fold<T> fd{r, V.q, r_other, coef(H, lslot(l, S_DR), dq_prev, 1.0)};
+                T* rn = r_other;
+                z = mgcycle(H, Hh, l, rn, 2, V.q, &fd);
+                r_other = const_cast<T*>(r);
+                r = rn;
+            }
+            dir_apply_fold(H, V, z, r, it, l);
+            std::swap(V.d, V.d2);
+        }
+        const int dq_last = lslot(l, ((kit - 1) & 1) ? S_DQ1 : S_DQ0);
+        k_update_xr<T><<<lin_grid(V.n), kBlock, 0, H->stream>>>((int)V.n, V.xk, V.d, (T*)nullptr, (const T*)nullptr,
+                                                             coef(H, lslot(l, S_DR), dq_last, 1.0), kit == 1, 1, 0,
+                                                             red(H, G_FN2), (float*)nullptr, 1);
+        check_launch();
+        return V.xk;
+    }
     for (int it = 0; it < kit; ++it) {
         T* z = mgcycle(H, Hh, l, V.rhs, it > 0 ? 2 : 0, V.q);
         dir_apply(H, V, false, z, it, l, false);
@@ -1729,6 +1835,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_RWSXCD")) p.rwsxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWCROWS")) p.rwcrows = atoi(s) <= 4 ? 4 : 8;
     if (const char* s = getenv("PP_EBLOCKS")) p.eblocks = std::max(64, std::min(kMaxPartialBlocks, atoi(s)));
+    if (const char* s = getenv("PP_KFOLD")) p.kfold = atoi(s) != 0;
     if (const char* s = getenv("PP_RWCBLOCKS")) p.rwcblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWCXCD")) p.rwcxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
