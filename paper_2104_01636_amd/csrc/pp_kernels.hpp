@@ -639,69 +639,120 @@ __global__ void __launch_bounds__(kBlock) k_level_finish(int nx, int ny, int nz,
     }
 }
 
-// Dense inverse of K + (mean D / n) 1 1^T for the coarsest level (one block,
-// Gauss-Jordan without pivoting: the matrix is symmetric positive definite).
-// work holds n x 2n doubles.
-__global__ void __launch_bounds__(kBlock) k_dense_inverse(int nx, int ny, int nz, const double* __restrict__ wx,
-                                                         const double* __restrict__ wy, const double* __restrict__ wz,
-                                                         double* __restrict__ work, double* __restrict__ M64,
-                                                         float* __restrict__ M32)
+// Dense inverse of K + (mean D / n) 1 1^T for the coarsest level (n <= kDenseRows;
+// symmetric positive definite, so Gauss-Jordan elimination needs no pivoting).
+// One block; thread t holds kDenseSeg consecutive entries of row t / kDenseSegs
+// in registers.  The matrix is inverted in place: for each pivot p (with the old
+// pivot row and column) a_pp <- 1 / a_pp, a_pj <- a_pj / a_pp, a_ip <- -a_ip / a_pp
+// and a_ij <- a_ij - a_ip a_pj / a_pp elsewhere.  The pivot row and column are
+// published in LDS by the threads that hold them, double-buffered: the holders of
+// row and column p + 1 publish them as soon as step p has updated them, so each
+// step takes one barrier.
+constexpr int kDenseRows = 128;
+constexpr int kDenseThreads = 1024;
+constexpr int kDenseSeg = kDenseRows * kDenseRows / kDenseThreads;  // entries per thread
+constexpr int kDenseSegs = kDenseRows / kDenseSeg;                  // threads per row
+__global__ void __launch_bounds__(kDenseThreads) k_dense_inverse(int nx, int ny, int nz, const double* __restrict__ wx,
+                                                                 const double* __restrict__ wy,
+                                                                 const double* __restrict__ wz, double* __restrict__ M64,
+                                                                 float* __restrict__ M32)
 {
     const int n = nx * ny * nz;
-    const int w2 = 2 * n;
+    const int sy = nx, sz = nx * ny;
+    __shared__ double diag[kDenseRows];
+    __shared__ double prow[2][kDenseRows], pcol[2][kDenseRows];
     __shared__ double dmean;
-    LevelView<double> L{nx, ny, nz, wx, wy, wz, nullptr};
-    for (int idx = threadIdx.x; idx < n * w2; idx += blockDim.x) work[idx] = 0.0;
+    const int i = threadIdx.x / kDenseSegs, j0 = (threadIdx.x % kDenseSegs) * kDenseSeg;
+    const bool own = i < n && j0 < n;
+    // cell i's neighbours and face weights, in the order the operator sums them
+    int nb[6];
+    double w[6];
+    double d = 0.0;
+    if (i < n) {
+        const int ci = i % nx, cj = (i / nx) % ny, ck = i / sz;
+        const int cb = ck > 0 ? i - sz : i + (nz - 1) * sz;
+        const int ct = ck < nz - 1 ? i + sz : i - (nz - 1) * sz;
+        nb[0] = ci > 0 ? i - 1 : -1;
+        w[0] = ci > 0 ? wx[i - 1] : 0.0;
+        nb[1] = ci < nx - 1 ? i + 1 : -1;
+        w[1] = ci < nx - 1 ? wx[i] : 0.0;
+        nb[2] = cj > 0 ? i - sy : -1;
+        w[2] = cj > 0 ? wy[i - sy] : 0.0;
+        nb[3] = cj < ny - 1 ? i + sy : -1;
+        w[3] = cj < ny - 1 ? wy[i] : 0.0;
+        nb[4] = cb;
+        w[4] = wz[cb];
+        nb[5] = ct;
+        w[5] = wz[i];
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+            if (nb[f] >= 0) d += w[f];
+        if (threadIdx.x % kDenseSegs == 0) diag[i] = d;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {  // the mean diagonal, summed in cell order
         double s = 0.0;
-        for (int c = 0; c < n; ++c) {
-            const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-            double ss, d;
-            nbsum<double>(L, i, j, k, c, [&](int, int, int, int) { return 0.0; }, ss, d);
-            s += d;
-        }
+        for (int c = 0; c < n; ++c) s += diag[c];
         dmean = s / n;
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-        double* row = work + c * w2;
-        for (int m = 0; m < n; ++m) row[m] = dmean / n;
-        const int sy = nx, sz = nx * ny;
-        const int cb = k > 0 ? c - sz : c + (nz - 1) * sz;
-        const int ct = k < nz - 1 ? c + sz : c - (nz - 1) * sz;
-        double d = 0.0;
-        if (i > 0) { row[c - 1] -= wx[c - 1]; d += wx[c - 1]; }
-        if (i < nx - 1) { row[c + 1] -= wx[c]; d += wx[c]; }
-        if (j > 0) { row[c - sy] -= wy[c - sy]; d += wy[c - sy]; }
-        if (j < ny - 1) { row[c + sy] -= wy[c]; d += wy[c]; }
-        row[cb] -= wz[cb]; d += wz[cb];
-        row[ct] -= wz[c]; d += wz[c];
-        row[c] += d;
-        row[n + c] = 1.0;
+    double a[kDenseSeg];
+    const double base = dmean / n;
+#pragma unroll
+    for (int u = 0; u < kDenseSeg; ++u) a[u] = base;
+    if (own) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+#pragma unroll
+            for (int u = 0; u < kDenseSeg; ++u)
+                if (nb[f] == j0 + u) a[u] -= w[f];
+        }
+#pragma unroll
+        for (int u = 0; u < kDenseSeg; ++u)
+            if (i == j0 + u) a[u] += d;
     }
+    // publish row and column 0
+    auto publish = [&](int p, int buf) {
+        if (!own || p >= n) return;
+        if (i == p) {
+#pragma unroll
+            for (int u = 0; u < kDenseSeg; ++u)
+                if (j0 + u < n) prow[buf][j0 + u] = a[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kDenseSeg; ++u)
+            if (j0 + u == p) pcol[buf][i] = a[u];
+    };
+    publish(0, 0);
     __syncthreads();
     for (int p = 0; p < n; ++p) {
-        const double piv = work[p * w2 + p];
-        __syncthreads();
-        for (int m = threadIdx.x; m < w2; m += blockDim.x) work[p * w2 + m] /= piv;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < n * w2; idx += blockDim.x) {
-            const int r = idx / w2, m = idx % w2;
-            if (r == p || m == p) continue;
-            work[idx] -= work[r * w2 + p] * work[p * w2 + m];
+        const int buf = p & 1;
+        const double rp = 1.0 / prow[buf][p];
+        if (own) {
+            if (i == p) {
+#pragma unroll
+                for (int u = 0; u < kDenseSeg; ++u) a[u] = (j0 + u == p) ? rp : a[u] * rp;
+            } else {
+                const double f = pcol[buf][i] * rp;
+#pragma unroll
+                for (int u = 0; u < kDenseSeg; ++u) {
+                    const int j = j0 + u;
+                    const double pj = prow[buf][j < n ? j : p];
+                    a[u] = (j == p) ? -f : a[u] - f * pj;
+                }
+            }
         }
-        __syncthreads();
-        for (int r = threadIdx.x; r < n; r += blockDim.x)
-            if (r != p) work[r * w2 + p] = 0.0;
+        publish(p + 1, buf ^ 1);
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, m = idx % n;
-        const double v = work[r * w2 + n + m];
-        M64[idx] = v;
-        M32[idx] = (float)v;
+    if (own) {
+#pragma unroll
+        for (int u = 0; u < kDenseSeg; ++u) {
+            if (j0 + u < n) {
+                M64[i * n + j0 + u] = a[u];
+                M32[i * n + j0 + u] = (float)a[u];
+            }
+        }
     }
 }
 

@@ -168,7 +168,7 @@ enum : int {
 static inline int lslot(int l, int s) { return l * kLevSlots + s; }
 
 constexpr int kMaxLev = 24;
-constexpr int kDenseMax = 128;
+constexpr int kDenseMax = kDenseRows;  // coarsening stops at the first level of at most this many cells
 static_assert(kDenseMax <= kTailDenseMax, "the tail's dense product covers the coarsest level");
 
 // ---------------------------------------------------------------- arena plan
@@ -273,6 +273,8 @@ struct Params {
     int rwcrows = 8;            // rows of a coarse-level row-wave block: 4 or 8
     int rwcblocks = 512;        // blocks of a coarse-level row-wave launch, at most
     int rwcxcd = 1;             // XCD-aware band order for them
+    int rwcblocks2 = 0;         // blocks of those launches on levels of at most rwcsmall cells (0: rwcblocks)
+    long rwcsmall = 524288;
     bool rwc = true;            // row-wave passes on float32 coarse levels with bfloat16 weights (nx 64..256)
     bool rwf = true;            // row-wave forms of the fused float32 finest-level passes (nx 128 or 256)
     int rwfrows = 12;           // their rows per block, ring included: 8, 12 or 16 (12: the most rows whose
@@ -305,7 +307,6 @@ struct Handle {
     // face weights per level (c64[0] holds beta_f of the finest level)
     std::vector<Level64> c64;
     std::vector<Level32> c32;
-    double* dense_work = nullptr;
     double* M64 = nullptr;
     float* M32 = nullptr;
 
@@ -468,7 +469,7 @@ static void levels_of(const pp_config& cfg, std::vector<int>& nx, std::vector<in
     while ((int)nx.size() < kMaxLev) {
         int a = nx.back(), b = ny.back(), c = nz.back();
         size_t n = (size_t)a * b * c;
-        if (n <= 64 || (a & 1) || (b & 1) || (c & 3)) break;
+        if (n <= (size_t)kDenseMax || (a & 1) || (b & 1) || (c & 3)) break;
         nx.push_back(a / 2);
         ny.push_back(b / 2);
         nz.push_back(c / 2);
@@ -522,11 +523,9 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
         }
     }
     const size_t nd = nn(nl - 1);
-    double* dense_work = nullptr;
     double* M64 = nullptr;
     float* M32 = nullptr;
     if (nl > 1 && nd <= (size_t)kDenseMax) {
-        dense_work = P.take<double>(2 * nd * nd);
         M64 = P.take<double>(nd * nd);
         M32 = P.take<float>(nd * nd);
     }
@@ -580,7 +579,7 @@ static size_t plan(Handle* H, const pp_config& cfg, char* base)
     if (H && base) {
         H->lnx = nx; H->lny = ny; H->lnz = nz; H->nlev = nl;
         H->c64 = c64; H->c32 = c32;
-        H->dense_work = dense_work; H->M64 = M64; H->M32 = M32;
+        H->M64 = M64; H->M32 = M32;
         H->f64 = f64; H->r64 = r64; H->x64 = x64; H->q64 = q64; H->r32 = r32;
         H->rho64 = rho64; H->rho32 = rho32;
         H->d = H->d_a = d_a; H->d2 = H->d_b = d_b;
@@ -832,7 +831,9 @@ static RwGeo rwc_geo(const Handle* H, const LevelView<T>& v)
         const int rows = H->prm.rwcrows;
         const int gy = (v.ny + rows - 1) / rows;
         int gz, kper;
-        rw_zsplit(H->prm.rwcxcd, gy, v.nz, H->prm.rwcblocks, false, gz, kper);
+        const int nb = (H->prm.rwcblocks2 > 0 && (size_t)v.nx * v.ny * v.nz <= (size_t)H->prm.rwcsmall) ? H->prm.rwcblocks2
+                                                                                                     : H->prm.rwcblocks;
+        rw_zsplit(H->prm.rwcxcd, gy, v.nz, nb, false, gz, kper);
         if ((size_t)gy * gz > (size_t)kMaxPartialBlocks) return g;
         g.grid = dim3(1, gy, gz);
         g.block = dim3(64, rows, 1);
@@ -1644,8 +1645,8 @@ static void set_density(Handle* H, const double* rho)
     }
     if (H->M64) {
         const int l = nl - 1;
-        k_dense_inverse<<<1, kBlock, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx, H->c64[l].wy,
-                                                     H->c64[l].wz, H->dense_work, H->M64, H->M32);
+        k_dense_inverse<<<1, kDenseThreads, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx,
+                                                            H->c64[l].wy, H->c64[l].wz, H->M64, H->M32);
         check_launch();
     }
     PP_HIP(hipEventRecord(H->ev1, H->stream));
@@ -1838,6 +1839,8 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_KFOLD")) p.kfold = atoi(s) != 0;
     if (const char* s = getenv("PP_RWCBLOCKS")) p.rwcblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWCXCD")) p.rwcxcd = atoi(s) != 0;
+    if (const char* s = getenv("PP_RWCBLOCKS2")) p.rwcblocks2 = std::max(0, std::min(kMaxPartialBlocks, atoi(s)));
+    if (const char* s = getenv("PP_RWCSMALL")) p.rwcsmall = std::max(0L, atol(s));
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
     if (const char* s = getenv("PP_RWC")) p.rwc = atoi(s) != 0;
     if (const char* s = getenv("PP_RWFXCD")) p.rwfxcd = atoi(s) != 0;

@@ -210,30 +210,40 @@ __device__ inline void pair_cell(int pk, int colour, int& c, int& fl)
     fl = odd ? ((f0 & ~(NB_W | NB_E)) | NB_W | ((f0 & 128) ? 0 : NB_E)) : ((f0 & ~NB_E) | NB_E);
 }
 
-// Half-sweep of the first level: kTailBatch pairs per thread and round (4 in
-// float32, 2 in float64, as registers allow), all loads of their cells issued
-// before any is computed (the cells of one colour are independent).
-template <class T, class A>
-__device__ inline void tail_half_first(const A& a, const int* pinfo, int np, int colour, T omega)
+// Half-sweep of the first level: NB pairs per thread and round, all loads of
+// their cells issued before any is computed (the cells of one colour are
+// independent).
+template <int NB, class T, class A>
+__device__ inline void tail_half_first_n(const A& a, const int* pinfo, int np, int colour, T omega)
 {
-    constexpr int kTailBatch = sizeof(T) == 4 ? 4 : 2;
-    for (int t = threadIdx.x; t < np; t += kTailBatch * kTailThreads) {
-        int c[kTailBatch], fl[kTailBatch];
-        TailIn<T> v[kTailBatch];
+    for (int t = threadIdx.x; t < np; t += NB * kTailThreads) {
+        int c[NB], fl[NB];
+        TailIn<T> v[NB];
 #pragma unroll
-        for (int b = 0; b < kTailBatch; ++b) {
+        for (int b = 0; b < NB; ++b) {
             const int tb = t + b * kTailThreads;
             pair_cell(pinfo[tb < np ? tb : t], colour, c[b], fl[b]);
             v[b] = tail_gather<T>(a, c[b], fl[b]);
         }
         __builtin_amdgcn_sched_barrier(0);  // keep all loads ahead of the arithmetic
-        T x[kTailBatch];
+        T x[NB];
 #pragma unroll
-        for (int b = 0; b < kTailBatch; ++b) x[b] = tail_update(v[b], omega);
+        for (int b = 0; b < NB; ++b) x[b] = tail_update(v[b], omega);
 #pragma unroll
-        for (int b = 0; b < kTailBatch; ++b)
+        for (int b = 0; b < NB; ++b)
             if (t + b * kTailThreads < np) a.xs[c[b]] = x[b];
     }
+}
+
+// The batch is the pairs per thread the level has, up to 4 in float32 and 2 in
+// float64 (as registers allow): a batch slot beyond the last pair would gather
+// again for nothing.
+template <class T, class A>
+__device__ inline void tail_half_first(const A& a, const int* pinfo, int np, int colour, T omega)
+{
+    if (np <= kTailThreads) tail_half_first_n<1, T>(a, pinfo, np, colour, omega);
+    else if (sizeof(T) == 8 || np <= 2 * kTailThreads) tail_half_first_n<2, T>(a, pinfo, np, colour, omega);
+    else tail_half_first_n<4, T>(a, pinfo, np, colour, omega);
     __syncthreads();
 }
 
@@ -377,10 +387,9 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
     const TailLevel<T>& V0 = D.L[0];
 
     // the dense inverse's entries this thread multiplies on the last level (see
-    // below); in float32 they are loaded now, so that their latency overlaps the
-    // cycle (in float64 they would not fit in registers beside it)
+    // below), loaded now so that their latency overlaps the staging
     constexpr int kPer = kTailDenseMax / kTailDenseSplit;
-    constexpr bool kEarly = sizeof(T) == 4;
+    constexpr bool kEarly = true;
     const int dr = threadIdx.x % kTailDenseMax, dc0 = (threadIdx.x / kTailDenseMax) * kPer;
     T m[kPer];
     auto load_m = [&]() {
@@ -394,23 +403,62 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
 
     // stage the operators of the later levels (and, with LDS0, the first level's
     // operator and right-hand side after them): every load of the cycle but the
-    // dense inverse is issued here
-    for (int l = 1; l <= last; ++l) {
-        const TailLevel<T>& V = D.L[l];
-        for (int c = threadIdx.x; c < V.n; c += kTailThreads) {
-            swx[V.off + c] = ldg(V.v.wx, c);
-            swy[V.off + c] = ldg(V.v.wy, c);
-            swz[V.off + c] = ldg(V.v.wz, c);
-            sid[V.off + c] = ldg(V.v.invd, c);
+    // dense inverse is issued here, all of them before the first is stored
+    {
+        static_assert(kTailSmallCells <= 2 * kTailThreads, "two staged cells per thread and group");
+        T lw[2][4], fw[2][5];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = threadIdx.x + u * kTailThreads;  // index into the later levels' LDS arrays
+            if (e < D.off0) {
+                // level of e: the last later level whose range starts at or before e
+                const T *px = nullptr, *py = nullptr, *pz = nullptr, *pi = nullptr;
+                int base = 0;
+#pragma unroll
+                for (int l = 1; l < kTailMaxLev; ++l) {
+                    if (l <= last && e >= D.L[l].off) {
+                        px = D.L[l].v.wx;
+                        py = D.L[l].v.wy;
+                        pz = D.L[l].v.wz;
+                        pi = D.L[l].v.invd;
+                        base = D.L[l].off;
+                    }
+                }
+                lw[u][0] = ldg(px, e - base);
+                lw[u][1] = ldg(py, e - base);
+                lw[u][2] = ldg(pz, e - base);
+                lw[u][3] = ldg(pi, e - base);
+            }
+            if constexpr (LDS0) {
+                if (e < V0.n) {
+                    fw[u][0] = ldg(V0.v.wx, e);
+                    fw[u][1] = ldg(V0.v.wy, e);
+                    fw[u][2] = ldg(V0.v.wz, e);
+                    fw[u][3] = ldg(V0.v.invd, e);
+                    fw[u][4] = ldg(V0.rhs, e);
+                }
+            }
         }
-    }
-    if constexpr (LDS0) {
-        for (int c = threadIdx.x; c < V0.n; c += kTailThreads) {
-            swx[D.off0 + c] = ldg(V0.v.wx, c);
-            swy[D.off0 + c] = ldg(V0.v.wy, c);
-            swz[D.off0 + c] = ldg(V0.v.wz, c);
-            sid[D.off0 + c] = ldg(V0.v.invd, c);
-            sf[D.off0 + c] = ldg(V0.rhs, c);
+        __builtin_amdgcn_sched_barrier(0);  // every load in flight before the first store waits
+        tail_pairs(V0.v, pinfo);            // formed while the loads are in flight
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = threadIdx.x + u * kTailThreads;
+            if (e < D.off0) {
+                swx[e] = lw[u][0];
+                swy[e] = lw[u][1];
+                swz[e] = lw[u][2];
+                sid[e] = lw[u][3];
+            }
+            if constexpr (LDS0) {
+                if (e < V0.n) {
+                    swx[D.off0 + e] = fw[u][0];
+                    swy[D.off0 + e] = fw[u][1];
+                    swz[D.off0 + e] = fw[u][2];
+                    sid[D.off0 + e] = fw[u][3];
+                    sf[D.off0 + e] = fw[u][4];
+                }
+            }
         }
     }
 #define PP_TAIL_SMALL(l)                                                                                          \
@@ -426,8 +474,7 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
         g = TailG<T>{V0.v.wx, V0.v.wy, V0.v.wz, V0.v.invd, V0.rhs, x0, V0.v.nx, V0.v.ny, V0.v.nz};
     }
     const int np0 = V0.n >> 1;
-    tail_pairs(V0.v, pinfo);
-    __syncthreads();  // also completes the staging above
+    __syncthreads();  // completes the staging and the pairs above
 #pragma unroll 2
     for (int t = threadIdx.x; t < np0; t += kTailThreads) {
         int c, fl;
@@ -466,7 +513,8 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
             tail_half_small(a, 1, om);
         }
         const TailS<T> cN = PP_TAIL_SMALL(l + 1);
-        tail_restrict<T>(a, cN.sf, cN.nx, cN.ny, D.L[l + 1].n);
+        if (D.L[l].n <= kTailThreads) tail_restrict_wide<T>(a, dpart, cN.sf, cN.nx, cN.ny, D.L[l + 1].n);
+        else tail_restrict<T>(a, cN.sf, cN.nx, cN.ny, D.L[l + 1].n);
     }
     {
         const TailS<T> b = PP_TAIL_SMALL(last);
