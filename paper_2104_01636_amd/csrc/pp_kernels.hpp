@@ -199,7 +199,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_first(LevelView<T> L, const T
 }
 
 // One SOR half-sweep over one colour, in place.  With NDOT > 0 the launch also
-// reduces sum(x) (and <x, q> for NDOT = 2) over all cells after the update.
+// reduces sum(x) (and <x, q> for NDOT >= 2, <x, f> for NDOT = 3) over all cells
+// after the update.
 template <class T, int NDOT, class TQ = T>
 __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
                                                        const TQ* __restrict__ q, Reduce R, T omega)
@@ -221,6 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T*
             }
             if constexpr (NDOT >= 1) acc[0] += (double)xv;
             if constexpr (NDOT >= 2) acc[1] += (double)xv * (double)q[c];
+            if constexpr (NDOT >= 3) acc[2] += (double)xv * (double)f[c];
         }
     }
     if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
@@ -278,7 +280,8 @@ __global__ void __launch_bounds__(kBlock) k_prolong_black(LevelView<T> L, const 
 
 // ---------------------------------------------------------------- Krylov steps
 
-// d_new = (z - m) + b * d_old, q = K d_new; reduces <d_new, q> and <d_new, r>.
+// d_new = (z - m) + b * d_old, q = K d_new; reduces <d_new, q> and <d_new, r>
+// (FINE: <d_new, q> only).
 // m = s[msum]/n (mean projection, finest level only) and b from the slots.  The
 // preconditioned residual z may be stored in a lower precision TZ than d and q.
 // FINE (the finest level's Krylov step): also applies the previous step's
@@ -293,7 +296,7 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* 
     const T b = use_beta ? (T)beta.get() : T(0);
     const T m = use_mean ? (T)mean.get() : T(0);
     const T ap = (FINE && use_beta) ? (T)aprev.get() : T(0);
-    double acc[2] = {0.0, 0.0};
+    double acc[FINE ? 1 : 2] = {};
     if (t.act) {
         auto dv = [&](int c, int, int, int) { return use_beta ? ((T)z[c] - m) + b * dold[c] : ((T)z[c] - m); };
         for (int k = t.k0; k < t.k1; ++k) {
@@ -305,13 +308,13 @@ __global__ void __launch_bounds__(kBlock) k_dir_apply(LevelView<T> L, const TZ* 
             dnew[c] = dc;
             q[c] = qc;
             acc[0] += (double)dc * (double)qc;
-            acc[1] += (double)dc * (double)r[c];
+            if constexpr (!FINE) acc[1] += (double)dc * (double)r[c];
             if constexpr (FINE) {
                 if (use_beta) x[c] = x[c] + ap * dold[c];
             }
         }
     }
-    reduce_finish<2>(acc, R);
+    reduce_finish<FINE ? 1 : 2>(acc, R);
 }
 
 // x += a d (or x = a d when first; only with do_x), r -= a q (unless skip_r);

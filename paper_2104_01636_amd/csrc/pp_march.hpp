@@ -322,7 +322,7 @@ struct OpFirstR {
 };
 
 template <class T, int NDOT, class TQ>
-struct OpHalf {  // one colour of a red-black SOR sweep in place; optional dots
+struct OpHalf {  // one colour of a red-black SOR sweep in place; dots sum(x), <x, q>, <x, f> (NDOT 1-3)
     const T* f;
     T* x;
     const TQ* q;
@@ -345,6 +345,7 @@ struct OpHalf {  // one colour of a red-black SOR sweep in place; optional dots
         }
         if constexpr (NDOT >= 1) acc[0] += (double)xv;
         if constexpr (NDOT >= 2) acc[1] += (double)xv * (double)e.q;
+        if constexpr (NDOT >= 3) acc[2] += (double)xv * (double)e.f;
     }
 };
 
@@ -374,11 +375,14 @@ struct OpProlongBlack {  // y = x + wc P e on red cells; black SOR update from t
 };
 
 // d_new = (z - m) + b d_old (d_new = z - m without BETA), q = K d_new; dots
-// <d,q> and <d,r>.  With BETA also the previous step's deferred update of x:
-// XU 2 x += ap * d_old (the finest level's Krylov step, FINE), XU 1 x = ap * d_old
-// (the second step of a K-cycle whose x starts at zero), XU 0 none.
+// <d,q> and <d,r> (FINE: <d,q> only; the finest level's step takes the
+// numerator of its step length from the cycle's <z, r>, and r is not read).
+// With BETA also the previous step's deferred update of x: XU 2 x += ap * d_old
+// (the finest level's Krylov step, FINE), XU 1 x = ap * d_old (the second step
+// of a K-cycle whose x starts at zero), XU 0 none.
 template <class T, class TZ, bool BETA, bool FINE, int XU = FINE ? 2 : 0>
 struct OpDir {
+    static constexpr bool kDR = !FINE;  // the <d,r> dot
     const TZ* z;
     const T* dold;
     const T* r;
@@ -390,7 +394,7 @@ struct OpDir {
     struct Ex { T r, x; };
     __device__ Raw load(int c, int, int, int) const { return {z[c], BETA ? dold[c] : T(0)}; }
     __device__ T val(const Raw& a) const { return BETA ? ((T)a.z - m) + b * a.d : ((T)a.z - m); }
-    __device__ Ex extra(int c) const { return {r[c], (XU == 2 && BETA) ? x[c] : T(0)}; }
+    __device__ Ex extra(int c) const { return {kDR ? r[c] : T(0), (XU == 2 && BETA) ? x[c] : T(0)}; }
     template <class A>
     __device__ void apply(int c, int, int, int, T vc, const Raw& own, const Ex& ev, const Stencil<T>& st, A& acc,
                           bool act) const
@@ -400,7 +404,7 @@ struct OpDir {
         dnew[c] = vc;
         q[c] = qc;
         acc[0] += (double)vc * (double)qc;
-        acc[1] += (double)vc * (double)ev.r;
+        if constexpr (kDR) acc[1] += (double)vc * (double)ev.r;
         if constexpr (XU == 2 && BETA) x[c] = ev.x + ap * own.d;
         if constexpr (XU == 1 && BETA) x[c] = ap * own.d;
     }
@@ -576,7 +580,7 @@ struct OpFirstRestrict {
 // it and those need the prolongated red values around them, so the march runs
 // with overlapped tiles (OVL) and the red update trails the black one by a plane,
 // as in OpFirstRestrict.  Writes z = y on black cells and the updated red cells;
-// dots sum(z) and <z, q> over the block's own cells.
+// dots sum(z), <z, q> and <z, f> (NDOT 1-3) over the block's own cells.
 template <class T, int NDOT, class TQ>
 struct OpProlongHalf {
     const T *f, *x, *e;
@@ -623,6 +627,7 @@ struct OpProlongHalf {
             z[cm1] = zv;
             if constexpr (NDOT >= 1) acc[0] += (double)zv;
             if constexpr (NDOT >= 2) acc[1] += (double)zv * (double)qm1;
+            if constexpr (NDOT >= 3) acc[2] += (double)zv * (double)fm1;
         }
         ym2 = ym1;
         ym1 = yv;
@@ -715,9 +720,10 @@ __global__ void __launch_bounds__((kMarchThreads<T, WM == kWRho>)) m_dir_apply(L
 {
     OpDir<T, TZ, BETA, FINE> op{z, dold, r, dnew, q, x, BETA ? (T)beta.get() : T(0), use_mean ? (T)mean.get() : T(0),
                                 (FINE && BETA) ? (T)aprev.get() : T(0)};
-    double acc[2] = {0.0, 0.0};
+    constexpr int NV = FINE ? 1 : 2;
+    double acc[NV] = {};
     march<T, BX, WM>(L, kper, xcd, op, acc);
-    reduce_finish<2>(acc, R);
+    reduce_finish<NV>(acc, R);
 }
 
 // y = A x on the finest level with the march kernels' weights (the same tiles,

@@ -282,9 +282,10 @@ __global__ void __launch_bounds__(64 * WPR * BY) r_dir_apply(LevelView<double> L
 {
     OpDir<double, TZ, BETA, FINE> op{z, dold, r, dnew, q, x, BETA ? beta.get() : 0.0, use_mean ? mean.get() : 0.0,
                                      (FINE && BETA) ? aprev.get() : 0.0};
-    double acc[2] = {0.0, 0.0};
-    march_rw<double, CPT, BY, decltype(op), double[2], kWRho, WPR>(L, kper, xcd, op, acc);
-    reduce_finish<2>(acc, R);
+    constexpr int NV = FINE ? 1 : 2;
+    double acc[NV] = {};
+    march_rw<double, CPT, BY, decltype(op), double[NV], kWRho, WPR>(L, kper, xcd, op, acc);
+    reduce_finish<NV>(acc, R);
 }
 
 template <int CPT, int BY, int WPR = 1>

@@ -157,8 +157,9 @@ static dim3 lin_grid(size_t n)
 // ---------------------------------------------------------------- slots
 
 enum : int {
-    kLevSlots = 8,      // per level: ZQ, SUMZ, DQ0, DQ1, DR, RR, RSUM
+    kLevSlots = 8,      // per level: ZQ, SUMZ, DQ0, DQ1, DR, RR, RSUM, DR1
     S_ZQ = 0, S_SUMZ = 1, S_DQ0 = 2, S_DQ1 = 3, S_DR = 4, S_RR = 5, S_RSUM = 6,
+    S_DR1 = 7,          // (the finest level's step-length numerators alternate between DR and DR1)
     G_BASE = 200,
     G_BSUM = G_BASE + 0, G_BBAD = G_BASE + 1, G_FN2 = G_BASE + 2, G_TRR = G_BASE + 3, G_TRSUM = G_BASE + 4,
     G_XSUM = G_BASE + 5, G_XBAD = G_BASE + 6, G_SCALE = G_BASE + 7, G_INVSCALE = G_BASE + 8, G_RHOSUM = G_BASE + 9,
@@ -273,8 +274,6 @@ struct Params {
     int rwcrows = 8;            // rows of a coarse-level row-wave block: 4 or 8
     int rwcblocks = 512;        // blocks of a coarse-level row-wave launch, at most
     int rwcxcd = 1;             // XCD-aware band order for them
-    int rwcblocks2 = 0;         // blocks of those launches on levels of at most rwcsmall cells (0: rwcblocks)
-    long rwcsmall = 524288;
     bool rwc = true;            // row-wave passes on float32 coarse levels with bfloat16 weights (nx 64..256)
     bool rwf = true;            // row-wave forms of the fused float32 finest-level passes (nx 128 or 256)
     int rwfrows = 12;           // their rows per block, ring included: 8, 12 or 16 (12: the most rows whose
@@ -295,6 +294,7 @@ struct Handle {
     Params prm;
     std::string err = "no error";
     bool have_density = false;
+    int zr_slot = 0;               // slot of <z, f> for a cycle's third dot (ndot 3)
 
     // geometry of levels
     std::vector<int> lnx, lny, lnz;
@@ -831,9 +831,7 @@ static RwGeo rwc_geo(const Handle* H, const LevelView<T>& v)
         const int rows = H->prm.rwcrows;
         const int gy = (v.ny + rows - 1) / rows;
         int gz, kper;
-        const int nb = (H->prm.rwcblocks2 > 0 && (size_t)v.nx * v.ny * v.nz <= (size_t)H->prm.rwcsmall) ? H->prm.rwcblocks2
-                                                                                                     : H->prm.rwcblocks;
-        rw_zsplit(H->prm.rwcxcd, gy, v.nz, nb, false, gz, kper);
+        rw_zsplit(H->prm.rwcxcd, gy, v.nz, H->prm.rwcblocks, false, gz, kper);
         if ((size_t)gy * gz > (size_t)kMaxPartialBlocks) return g;
         g.grid = dim3(1, gy, gz);
         g.block = dim3(64, rows, 1);
@@ -1145,7 +1143,7 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
 template <class T, class TQ>
 static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int colour, int ndot, const TQ* q, int l)
 {
-    Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
+    Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ), H->zr_slot);
     dim3 grid;
     {
         // reads x, f and the weights (or the density; the per-cell kernels also 1/D); writes one
@@ -1155,7 +1153,8 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
                                     (ndot >= 2 ? sizeof(TQ) : 0)));
         if (ndot == 0) grid = launch_half<T, 0, TQ>(H, V.v, f, x, colour, q, R);
         else if (ndot == 1) grid = launch_half<T, 1, TQ>(H, V.v, f, x, colour, q, R);
-        else grid = launch_half<T, 2, TQ>(H, V.v, f, x, colour, q, R);
+        else if (ndot == 2) grid = launch_half<T, 2, TQ>(H, V.v, f, x, colour, q, R);
+        else grid = launch_half<T, 3, TQ>(H, V.v, f, x, colour, q, R);
     }
     if (ndot > 0) finish(H, R, grid, ndot);
 }
@@ -1236,8 +1235,8 @@ static void cycle_pre(Handle* H, Lev<T>& V, int l, int nu, const T* f, T* x, T* 
 // Up leg of a cycle at level l: y = x + wc P e (injection), then nu sweeps
 // (black, then red) of K y = f, the first black half-sweep fused with the
 // prolongation (and, on a fused level, the red one too).  ndot: 0 none,
-// 1 sum(y), 2 sum(y) and <y, q>, reduced on the last half-sweep into level l's
-// slots.  Returns y.
+// 1 sum(y), 2 sum(y) and <y, q>, 3 also <y, f> (into H->zr_slot), reduced on the
+// last half-sweep into level l's slots.  Returns y.
 template <class T, class TQ>
 static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x, const T* e, T wc, T* y, int ndot,
                      const TQ* q)
@@ -1246,14 +1245,15 @@ static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x
     if (nu == 1 && H->prm.pfuse && fused(H, sizeof(T), V.n)) {
         // reads x, f, the weights (or the density), the coarse correction and q for the dot;
         // writes z
-        const Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ));
+        const Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ), H->zr_slot);
         dim3 grid;
         {
             TimeScope ts(H, fine ? kid<T>(KT_PROLONG_HALF) : -1,
                          (double)V.n * ((3.125 + weight_arrays(H, V.v)) * sizeof(T) + (ndot >= 2 ? sizeof(TQ) : 0)));
             if (ndot == 0) grid = launch_prolong_half<T, 0, TQ>(H, V.v, f, x, e, wc, y, q, R);
             else if (ndot == 1) grid = launch_prolong_half<T, 1, TQ>(H, V.v, f, x, e, wc, y, q, R);
-            else grid = launch_prolong_half<T, 2, TQ>(H, V.v, f, x, e, wc, y, q, R);
+            else if (ndot == 2) grid = launch_prolong_half<T, 2, TQ>(H, V.v, f, x, e, wc, y, q, R);
+            else grid = launch_prolong_half<T, 3, TQ>(H, V.v, f, x, e, wc, y, q, R);
         }
         if (ndot > 0) finish(H, R, grid, ndot);
         return y;
@@ -1274,8 +1274,8 @@ static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x
 
 
 // One multigrid cycle at level l for right-hand side f; returns the buffer holding
-// the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, reduced on the last
-// half-sweep into level l's slots.
+// the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, 3 also <z, f> (into
+// H->zr_slot), reduced on the last half-sweep into level l's slots.
 template <class T, class TQ = T>
 static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ* q, const Fold<T>* fold = nullptr)
 {
@@ -1472,11 +1472,16 @@ static dim3 fine_grid(const Handle* H, size_t n)
 
 // One step of the finest-level flexible CG, float64 throughout (x, r, d, q and
 // the operator from rho), preconditioned by one multigrid cycle in precision P:
-// z = M r (the cycle also reduces sum(z) and <z, q_old>), d = (z - mean z) +
-// beta d_old, q = K d with <d, q> and <d, r>, then r -= alpha q (and the float32
-// copy of r for a float32 cycle) with ||r||^2, alpha = <d, r> / <d, q>.  The x
-// update is deferred: step k applies x += alpha_{k-1} d_{k-1} while it reads
-// d_{k-1} anyway, and fcg() applies the last one.
+// z = M r (the cycle also reduces sum(z), <z, q_old> and <z, r>), d = (z - mean z)
+// + beta d_old, q = K d with <d, q>, then r -= alpha q (and the float32 copy of r
+// for a float32 cycle) with ||r||^2, alpha = <z, r> / <d, q>.  <z, r> equals
+// <d, r> up to rounding (r is orthogonal to d_old after the previous step and
+// sums to zero), so the direction update need not read r.  The cycle's r is the
+// float32 copy in the refined form.  The x update is deferred: step k applies
+// x += alpha_{k-1} d_{k-1} while it reads d_{k-1} anyway, and fcg() applies the
+// last one.  The numerators <z, r> of consecutive steps alternate between two
+// slots (step k's cycle writes its own before step k's direction update reads
+// step k-1's).
 template <class P>
 static void krylov_step(Handle* H, Hier<P>& Hh, int k)
 {
@@ -1484,23 +1489,26 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
     const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
-    P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, k > 0 ? 2 : 1, H->q64);
+    const int zr_prev = lslot(0, (k & 1) ? S_DR : S_DR1);
+    const int zr_cur = lslot(0, (k & 1) ? S_DR1 : S_DR);
+    // the first step has no q_old: its <z, q> (unused) is taken against r instead
+    H->zr_slot = zr_cur;
+    P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, 3, k > 0 ? H->q64 : H->r64);
     {
         const LevelView<double> v = fine64(H);
-        // alpha of the previous step is read before this launch's totals replace DR
-        const Reduce R = red(H, dq_cur, lslot(0, S_DR));
+        const Reduce R = red(H, dq_cur);
         dim3 grid;
         {
-            // reads z, the float64 weights (or density), r and, after the first step, d_old and x;
+            // reads z, the float64 weights (or density) and, after the first step, d_old and x;
             // writes d, q (and x)
             TimeScope ts(H, kid<double>(KT_DIR_APPLY),
-                         (double)n0 * ((double)sizeof(P) + (k > 0 ? 48.0 : 24.0) + 8.0 * weight_arrays(H, v)));
+                         (double)n0 * ((double)sizeof(P) + (k > 0 ? 40.0 : 16.0) + 8.0 * weight_arrays(H, v)));
             grid = launch_dir<double, P, true>(H, v, z, H->d, H->d2, H->q64, H->r64, H->x64,
                                                coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
                                                coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1,
-                                               coef(H, lslot(0, S_DR), dq_prev, 1.0), R);
+                                               coef(H, zr_prev, dq_prev, 1.0), R);
         }
-        finish(H, R, grid, 2);
+        finish(H, R, grid, 1);
     }
     {
         const Reduce R = red_host(H, lslot(0, S_RR), lslot(0, S_RSUM));
@@ -1508,7 +1516,7 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
             // reads r and q; writes r and the float32 copy of r
             TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (24.0 + (H->r32 ? 4.0 : 0.0)));
             k_update_xr<double><<<fine_grid(H, n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
-                                                                          coef(H, lslot(0, S_DR), dq_cur, 1.0), 0, 0, 1, R,
+                                                                          coef(H, zr_cur, dq_cur, 1.0), 0, 0, 1, R,
                                                                           H->r32, 0);
             check_launch();
         }
@@ -1583,7 +1591,7 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
     if (k > 0) {  // the deferred x += alpha d of the last step
         const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
         const int last = k - 1;
-        const Coefs a = coef(H, lslot(0, S_DR), lslot(0, (last & 1) ? S_DQ1 : S_DQ0), 1.0);
+        const Coefs a = coef(H, lslot(0, (last & 1) ? S_DR1 : S_DR), lslot(0, (last & 1) ? S_DQ1 : S_DQ0), 1.0);
         k_update_xr<double><<<fine_grid(H, n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d, H->r64, H->q64, a, 0, 1, 0,
                                                                     red(H, G_FN2), (float*)nullptr, 1);
         check_launch();
@@ -1839,8 +1847,6 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_KFOLD")) p.kfold = atoi(s) != 0;
     if (const char* s = getenv("PP_RWCBLOCKS")) p.rwcblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWCXCD")) p.rwcxcd = atoi(s) != 0;
-    if (const char* s = getenv("PP_RWCBLOCKS2")) p.rwcblocks2 = std::max(0, std::min(kMaxPartialBlocks, atoi(s)));
-    if (const char* s = getenv("PP_RWCSMALL")) p.rwcsmall = std::max(0L, atol(s));
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
     if (const char* s = getenv("PP_RWC")) p.rwc = atoi(s) != 0;
     if (const char* s = getenv("PP_RWFXCD")) p.rwfxcd = atoi(s) != 0;
