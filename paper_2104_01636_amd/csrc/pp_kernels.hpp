@@ -585,6 +585,106 @@ __global__ void __launch_bounds__(kBlock) k_coarsen_rho(int nx, int ny, int nz, 
     }
 }
 
+// The set-up passes over the finest density in one launch (density-formed
+// finest weights, a coarse level below it): per coarse cell, for its 8 fine
+// cells the handle's float64 and float32 copies of the density and 1/D (as
+// k_fine_diag forms it with D64, else as k_fine_diag32 forms it), the first
+// coarse level's face weights (as k_coarsen_rho forms them), and the count of
+// density values that are not finite and > 0 (one value reduced).  Each fine
+// value is formed from the same operands in the same order as by those
+// kernels, so the results are the same bit for bit.
+template <bool D64>
+__global__ void __launch_bounds__(kBlock) k_fine_setup(int nx, int ny, int nz, const double* __restrict__ rho,
+                                                      double* __restrict__ rho64, float* __restrict__ rho32,
+                                                      double* __restrict__ invd64, float* __restrict__ invd32,
+                                                      double* __restrict__ wx, double* __restrict__ wy,
+                                                      double* __restrict__ wz, int kper, Reduce R)
+{
+    const int cnx = nx >> 1, cny = ny >> 1, cnz = nz >> 1;
+    Tile t = tile(cnx, cny, cnz, kper);
+    double acc[1] = {0.0};
+    if (t.act) {
+        const int i0 = 2 * t.i - 1, j0 = 2 * t.j - 1;  // fine index of v's slot 0 in x and y
+        auto beta32 = [](float a, float b) { return 2.0f * __builtin_amdgcn_rcpf(a + b); };
+        for (int K = t.k0; K < t.k1; ++K) {
+            const int k0 = 2 * K - 1;
+            // v[c][b][a]: the density at fine (i0 + a, j0 + b, k0 + c), a, b, c in 0..3, loaded for
+            // the 2 x 2 x 2 cells of the coarse cell and their face neighbours (x and y clamped at
+            // the walls, where the value is not used; z periodic)
+            double v[4][4][4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int k = k0 + c < 0 ? k0 + c + nz : (k0 + c >= nz ? k0 + c - nz : k0 + c);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int j = max(0, min(ny - 1, j0 + b));
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int outside = (a == 0 || a == 3) + (b == 0 || b == 3) + (c == 0 || c == 3);
+                        if (outside > 1) continue;
+                        const int i = max(0, min(nx - 1, i0 + a));
+                        v[c][b][a] = rho[cell(nx, ny, i, j, k)];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 1; c < 3; ++c) {
+#pragma unroll
+                for (int b = 1; b < 3; ++b) {
+#pragma unroll
+                    for (int a = 1; a < 3; ++a) {
+                        const int i = i0 + a, j = j0 + b, k = k0 + c;
+                        const int ci = cell(nx, ny, i, j, k);
+                        const double r = v[c][b][a];
+                        acc[0] += (!(r - r == 0.0) || !(r > 0.0)) ? 1.0 : 0.0;
+                        rho64[ci] = r;
+                        if (rho32) rho32[ci] = (float)r;
+                        if constexpr (D64) {
+                            double d = 0.0;
+                            if (i > 0) d += 2.0 / (v[c][b][a - 1] + r);
+                            if (i < nx - 1) d += 2.0 / (r + v[c][b][a + 1]);
+                            if (j > 0) d += 2.0 / (v[c][b - 1][a] + r);
+                            if (j < ny - 1) d += 2.0 / (r + v[c][b + 1][a]);
+                            d += 2.0 / (v[c - 1][b][a] + r);
+                            d += 2.0 / (r + v[c + 1][b][a]);
+                            const double inv = 1.0 / d;
+                            invd64[ci] = inv;
+                            if (invd32) invd32[ci] = (float)inv;
+                        } else {
+                            const float rf = (float)r;
+                            float d = 0.0f;
+                            if (i > 0) d += beta32((float)v[c][b][a - 1], rf);
+                            if (i < nx - 1) d += beta32(rf, (float)v[c][b][a + 1]);
+                            if (j > 0) d += beta32((float)v[c][b - 1][a], rf);
+                            if (j < ny - 1) d += beta32(rf, (float)v[c][b + 1][a]);
+                            d += beta32((float)v[c - 1][b][a], rf);
+                            d += beta32(rf, (float)v[c + 1][b][a]);
+                            invd32[ci] = __builtin_amdgcn_rcpf(d);
+                        }
+                    }
+                }
+            }
+            // coarse face weights: sums of the four fine beta_f across each face, in
+            // k_coarsen_rho's order (a over y or x, b over z or y)
+            double sx = 0.0, syw = 0.0, szw = 0.0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    sx += 2 * t.i + 1 < nx - 1 ? 2.0 / (v[b + 1][a + 1][2] + v[b + 1][a + 1][3]) : 0.0;
+                    syw += 2 * t.j + 1 < ny - 1 ? 2.0 / (v[b + 1][2][a + 1] + v[b + 1][3][a + 1]) : 0.0;
+                    szw += 2.0 / (v[2][b + 1][a + 1] + v[3][b + 1][a + 1]);
+                }
+            }
+            const int cc = cell(cnx, cny, t.i, t.j, K);
+            wx[cc] = sx;
+            wy[cc] = syw;
+            wz[cc] = szw;
+        }
+    }
+    reduce_finish<1>(acc, R);
+}
+
 // Next coarse level: each coarse face weight is the sum of the four fine face
 // weights that form it.
 __global__ void __launch_bounds__(kBlock) k_coarsen(int nx, int ny, int nz, const double* __restrict__ fx,
@@ -644,13 +744,15 @@ __global__ void __launch_bounds__(kBlock) k_level_finish(int nx, int ny, int nz,
 
 // Dense inverse of K + (mean D / n) 1 1^T for the coarsest level (n <= kDenseRows;
 // symmetric positive definite, so Gauss-Jordan elimination needs no pivoting).
-// One block; thread t holds kDenseSeg consecutive entries of row t / kDenseSegs
-// in registers.  The matrix is inverted in place: for each pivot p (with the old
-// pivot row and column) a_pp <- 1 / a_pp, a_pj <- a_pj / a_pp, a_ip <- -a_ip / a_pp
-// and a_ij <- a_ij - a_ip a_pj / a_pp elsewhere.  The pivot row and column are
-// published in LDS by the threads that hold them, double-buffered: the holders of
-// row and column p + 1 publish them as soon as step p has updated them, so each
-// step takes one barrier.
+// One block; thread t holds, in registers, kDenseSeg entries of row
+// t / kDenseSegs: the columns s + kDenseSegs u (s = t mod kDenseSegs), so that
+// the threads of a wavefront reading one u of the pivot row read consecutive
+// words (distinct LDS banks).  The matrix is inverted in place: for each pivot
+// p (with the old pivot row and column) a_pp <- 1 / a_pp, a_pj <- a_pj / a_pp,
+// a_ip <- -a_ip / a_pp and a_ij <- a_ij - a_ip a_pj / a_pp elsewhere.  The pivot
+// row and column are published in LDS by the threads that hold them,
+// double-buffered: the holders of row and column p + 1 publish them as soon as
+// step p has updated them, so each step takes one barrier.
 constexpr int kDenseRows = 128;
 constexpr int kDenseThreads = 1024;
 constexpr int kDenseSeg = kDenseRows * kDenseRows / kDenseThreads;  // entries per thread
@@ -665,13 +767,14 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_inverse(int nx, int ny,
     __shared__ double diag[kDenseRows];
     __shared__ double prow[2][kDenseRows], pcol[2][kDenseRows];
     __shared__ double dmean;
-    const int i = threadIdx.x / kDenseSegs, j0 = (threadIdx.x % kDenseSegs) * kDenseSeg;
-    const bool own = i < n && j0 < n;
+    const int i = threadIdx.x / kDenseSegs, s0 = threadIdx.x % kDenseSegs;
+    const bool own = i < n;
+    auto col = [&](int u) { return s0 + kDenseSegs * u; };
     // cell i's neighbours and face weights, in the order the operator sums them
     int nb[6];
     double w[6];
     double d = 0.0;
-    if (i < n) {
+    if (own) {
         const int ci = i % nx, cj = (i / nx) % ny, ck = i / sz;
         const int cb = ck > 0 ? i - sz : i + (nz - 1) * sz;
         const int ct = ck < nz - 1 ? i + sz : i - (nz - 1) * sz;
@@ -690,13 +793,13 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_inverse(int nx, int ny,
 #pragma unroll
         for (int f = 0; f < 6; ++f)
             if (nb[f] >= 0) d += w[f];
-        if (threadIdx.x % kDenseSegs == 0) diag[i] = d;
+        if (s0 == 0) diag[i] = d;
     }
     __syncthreads();
     if (threadIdx.x == 0) {  // the mean diagonal, summed in cell order
-        double s = 0.0;
-        for (int c = 0; c < n; ++c) s += diag[c];
-        dmean = s / n;
+        double sum = 0.0;
+        for (int c = 0; c < n; ++c) sum += diag[c];
+        dmean = sum / n;
     }
     __syncthreads();
     double a[kDenseSeg];
@@ -708,42 +811,52 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_inverse(int nx, int ny,
         for (int f = 0; f < 6; ++f) {
 #pragma unroll
             for (int u = 0; u < kDenseSeg; ++u)
-                if (nb[f] == j0 + u) a[u] -= w[f];
+                if (nb[f] == col(u)) a[u] -= w[f];
         }
 #pragma unroll
         for (int u = 0; u < kDenseSeg; ++u)
-            if (i == j0 + u) a[u] += d;
+            if (i == col(u)) a[u] += d;
     }
-    // publish row and column 0
+    // row p and column p of the current matrix into LDS buffer buf (entries past
+    // n are never read)
     auto publish = [&](int p, int buf) {
-        if (!own || p >= n) return;
+        if (p >= n) return;
         if (i == p) {
 #pragma unroll
-            for (int u = 0; u < kDenseSeg; ++u)
-                if (j0 + u < n) prow[buf][j0 + u] = a[u];
+            for (int u = 0; u < kDenseSeg; ++u) prow[buf][col(u)] = a[u];
         }
+        const int q = p / kDenseSegs;
+        double v = a[0];
 #pragma unroll
-        for (int u = 0; u < kDenseSeg; ++u)
-            if (j0 + u == p) pcol[buf][i] = a[u];
+        for (int u = 1; u < kDenseSeg; ++u) v = (u == q) ? a[u] : v;
+        if (s0 == p % kDenseSegs) pcol[buf][i] = v;
     };
     publish(0, 0);
     __syncthreads();
     for (int p = 0; p < n; ++p) {
         const int buf = p & 1;
-        const double rp = 1.0 / prow[buf][p];
-        if (own) {
-            if (i == p) {
+        // every LDS read of the step is issued before any result is used (columns
+        // past n read entries that are never written; their results are not stored)
+        double pj[kDenseSeg];
 #pragma unroll
-                for (int u = 0; u < kDenseSeg; ++u) a[u] = (j0 + u == p) ? rp : a[u] * rp;
-            } else {
-                const double f = pcol[buf][i] * rp;
+        for (int u = 0; u < kDenseSeg; ++u) pj[u] = prow[buf][col(u)];
+        const double piv = prow[buf][p];
+        const double aip = pcol[buf][i];
+        const double rp = 1.0 / piv;
+        const double f = aip * rp;
+        if (i == p) {
 #pragma unroll
-                for (int u = 0; u < kDenseSeg; ++u) {
-                    const int j = j0 + u;
-                    const double pj = prow[buf][j < n ? j : p];
-                    a[u] = (j == p) ? -f : a[u] - f * pj;
-                }
-            }
+            for (int u = 0; u < kDenseSeg; ++u) a[u] = a[u] * rp;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kDenseSeg; ++u) a[u] = a[u] - f * pj[u];
+        }
+        if (s0 == p % kDenseSegs) {  // the entry in column p
+            const int q = p / kDenseSegs;
+            const double val = i == p ? rp : -f;
+#pragma unroll
+            for (int u = 0; u < kDenseSeg; ++u)
+                if (u == q) a[u] = val;
         }
         publish(p + 1, buf ^ 1);
         __syncthreads();
@@ -751,9 +864,9 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_inverse(int nx, int ny,
     if (own) {
 #pragma unroll
         for (int u = 0; u < kDenseSeg; ++u) {
-            if (j0 + u < n) {
-                M64[i * n + j0 + u] = a[u];
-                M32[i * n + j0 + u] = (float)a[u];
+            if (col(u) < n) {
+                M64[i * n + col(u)] = a[u];
+                M32[i * n + col(u)] = (float)a[u];
             }
         }
     }

@@ -268,6 +268,9 @@ struct Params {
     int rwsxcd = 0;
     int eblocks = 512;          // blocks of the finest-level r/q update, at most (164 us with 512, 185
                                 // with 2048, 215 with 256)
+    bool onepass = true;        // the finest level's set-up and the first coarse level's weights in one
+                                // pass over the density (k_fine_setup; the same values as the separate
+                                // passes)
     bool kfold = true;          // K-cycle steps on row-wave float32 levels without a separate x/r update:
                                 // r -= alpha q rides on the next step's first sweep, x += alpha d on
                                 // the next step's direction update
@@ -332,6 +335,11 @@ struct Handle {
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double setup_ms = 0.0;
+    // the coarsest dense inverse runs on a second stream (one work-group): it overlaps the end of
+    // the set-up and the start of the next solve, which waits for it before its first cycle
+    hipStream_t side = nullptr;
+    hipEvent_t ev_coarse = nullptr, ev_dense = nullptr;
+    bool dense_pending = false;
 
     bool use_graphs = true;  // replay Krylov steps from captured graphs (needs a non-null stream)
 
@@ -1608,20 +1616,41 @@ static void set_density(Handle* H, const double* rho)
     const int nl = H->nlev;
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     PP_HIP(hipEventRecord(H->ev0, H->stream));
-    // validate: finite and > 0
-    k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, 1, red(H, G_RHOSUM, G_RHOBAD));
-    check_launch();
-    finish(H, red_host(H, G_RHOSUM, G_RHOBAD), lin_grid(n0), 2);
-    fetch_slots(H, G_RHOSUM, 2);
-    if (H->host_slots[G_RHOBAD] != 0.0)
-        throw Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
-                                         " entries that are not finite or not > 0");
-    // the handle's own copies of the density (the caller keeps rho)
-    k_take_density<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, H->rho64, H->rho32);
-    check_launch();
     const bool fine_rho = weights_from_density(H->prm);
+    auto bad_density = [&]() {
+        return Fail(PP_ERR_NONFINITE, "density has " + std::to_string((long long)H->host_slots[G_RHOBAD]) +
+                                          " entries that are not finite or not > 0");
+    };
+    // one pass over the density for the finest level and the first coarse one (the validation's
+    // count is checked at the end; the handle holds no density until then)
+    const bool one_pass = fine_rho && nl >= 2 && H->prm.onepass;
+    if (one_pass) {
+        const Geo g = geo(H->lnx[1], H->lny[1], H->lnz[1]);
+        const Reduce R = red(H, G_RHOBAD);
+        if (H->c64[0].invd)
+            k_fine_setup<true><<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, rho, H->rho64, H->rho32,
+                                                                  H->c64[0].invd, H->c32[0].invd, H->c64[1].wx,
+                                                                  H->c64[1].wy, H->c64[1].wz, g.kper, R);
+        else
+            k_fine_setup<false><<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, rho, H->rho64, H->rho32,
+                                                                   nullptr, H->c32[0].invd, H->c64[1].wx, H->c64[1].wy,
+                                                                   H->c64[1].wz, g.kper, R);
+        check_launch();
+        finish(H, red_host(H, G_RHOBAD), g.grid, 1);
+    } else {
+        // validate: finite and > 0
+        k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, 1, red(H, G_RHOSUM, G_RHOBAD));
+        check_launch();
+        finish(H, red_host(H, G_RHOSUM, G_RHOBAD), lin_grid(n0), 2);
+        fetch_slots(H, G_RHOSUM, 2);
+        if (H->host_slots[G_RHOBAD] != 0.0) throw bad_density();
+        // the handle's own copies of the density (the caller keeps rho)
+        k_take_density<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rho, H->rho64, H->rho32);
+        check_launch();
+    }
     for (int l = 0; l < nl; ++l) {
         Geo g = geo(H->lnx[l], H->lny[l], H->lnz[l]);
+        if (one_pass && l == 0) continue;
         if (l == 0 && fine_rho) {
             // no stored finest weights: 1/D from the density (float64 for the float64 cycle, float32
             // as the float32 passes form their weights for the float32 cycle)
@@ -1637,6 +1666,9 @@ static void set_density(Handle* H, const double* rho)
         if (l == 0)
             k_fine_faces<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, rho, H->c64[0].wx, H->c64[0].wy,
                                                             H->c64[0].wz, g.kper);
+        else if (l == 1 && one_pass) {
+            // formed by k_fine_setup
+        }
         else if (l == 1 && fine_rho)
             k_coarsen_rho<<<g.grid, g.block, 0, H->stream>>>(cfg.nx, cfg.ny, cfg.nz, H->rho64, H->lnx[1], H->lny[1],
                                                              H->lnz[1], H->c64[1].wx, H->c64[1].wy, H->c64[1].wz, g.kper);
@@ -1652,13 +1684,23 @@ static void set_density(Handle* H, const double* rho)
         check_launch();
     }
     if (H->M64) {
+        // after the coarsest weights (and every use of the previous inverse: the same stream) on
+        // the second stream; the next solve waits for it before its first cycle
         const int l = nl - 1;
-        k_dense_inverse<<<1, kDenseThreads, 0, H->stream>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx,
-                                                            H->c64[l].wy, H->c64[l].wz, H->M64, H->M32);
+        PP_HIP(hipEventRecord(H->ev_coarse, H->stream));
+        PP_HIP(hipStreamWaitEvent(H->side, H->ev_coarse, 0));
+        k_dense_inverse<<<1, kDenseThreads, 0, H->side>>>(H->lnx[l], H->lny[l], H->lnz[l], H->c64[l].wx,
+                                                          H->c64[l].wy, H->c64[l].wz, H->M64, H->M32);
         check_launch();
+        PP_HIP(hipEventRecord(H->ev_dense, H->side));
+        H->dense_pending = true;
     }
     PP_HIP(hipEventRecord(H->ev1, H->stream));
     PP_HIP(hipEventSynchronize(H->ev1));
+    if (one_pass) {
+        fetch_slots(H, G_RHOBAD, 1);
+        if (H->host_slots[G_RHOBAD] != 0.0) throw bad_density();
+    }
     float ms = 0.f;
     PP_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1));
     H->setup_ms = ms;
@@ -1759,6 +1801,10 @@ static int solve(Handle* H, const double* rhs, double* p, pp_stats* st)
             if (rel <= cfg.tol) { converged = true; break; }
             if (!(rel == rel)) throw Fail(PP_ERR_NONFINITE, "non-finite residual during the iteration");
             if (iters >= max_it || restarts >= 50) break;
+            if (H->dense_pending) {  // the coarsest inverse of the last set-up (second stream)
+                PP_HIP(hipStreamWaitEvent(H->stream, H->ev_dense, 0));
+                H->dense_pending = false;
+            }
             if (H->prm.mg_solver) {
                 // the paper's form: multigrid cycles with red-black SOR as the solver, x += M (f - K x)
                 double* z = mgcycle<double, double>(H, H->h64, 0, H->r64, 0, nullptr);
@@ -1845,6 +1891,7 @@ static void read_env(Params& p, const pp_config* cfg = nullptr)
     if (const char* s = getenv("PP_RWCROWS")) p.rwcrows = atoi(s) <= 4 ? 4 : 8;
     if (const char* s = getenv("PP_EBLOCKS")) p.eblocks = std::max(64, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_KFOLD")) p.kfold = atoi(s) != 0;
+    if (const char* s = getenv("PP_ONEPASS")) p.onepass = atoi(s) != 0;
     if (const char* s = getenv("PP_RWCBLOCKS")) p.rwcblocks = std::max(8, std::min(kMaxPartialBlocks, atoi(s)));
     if (const char* s = getenv("PP_RWCXCD")) p.rwcxcd = atoi(s) != 0;
     if (const char* s = getenv("PP_RWF")) p.rwf = atoi(s) != 0;
@@ -2038,6 +2085,9 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
         }
         PP_HIP(hipEventCreate(&H->ev0));
         PP_HIP(hipEventCreate(&H->ev1));
+        PP_HIP(hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking));
+        PP_HIP(hipEventCreateWithFlags(&H->ev_coarse, hipEventDisableTiming));
+        PP_HIP(hipEventCreateWithFlags(&H->ev_dense, hipEventDisableTiming));
         PP_HIP(hipMemsetAsync(H->slots, 0, kSlots * sizeof(double), H->stream));
         {
             double one = 1.0;
@@ -2054,6 +2104,9 @@ int pp_create(const pp_config* cfg, void* hip_stream, pp_handle* out)
         if (H->host_slots) (void)hipHostFree(H->host_slots);
         if (H->ev0) (void)hipEventDestroy(H->ev0);
         if (H->ev1) (void)hipEventDestroy(H->ev1);
+        if (H->side) (void)hipStreamDestroy(H->side);
+        if (H->ev_coarse) (void)hipEventDestroy(H->ev_coarse);
+        if (H->ev_dense) (void)hipEventDestroy(H->ev_dense);
         delete h;
         return rc;
     }
@@ -2200,6 +2253,7 @@ int pp_destroy(pp_handle h)
     Handle* H = &h->h;
     (void)hipSetDevice(H->device);
     if (H->stream) (void)hipStreamSynchronize(H->stream);
+    if (H->side) (void)hipStreamSynchronize(H->side);
     if (H->arena) (void)hipFree(H->arena);
     if (H->host_slots) (void)hipHostFree(H->host_slots);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
@@ -2207,6 +2261,9 @@ int pp_destroy(pp_handle h)
     for (hipEvent_t e : H->ev_pool) (void)hipEventDestroy(e);
     drop_graphs(H);
     if (H->stream) (void)hipStreamDestroy(H->stream);
+    if (H->side) (void)hipStreamDestroy(H->side);
+    if (H->ev_coarse) (void)hipEventDestroy(H->ev_coarse);
+    if (H->ev_dense) (void)hipEventDestroy(H->ev_dense);
     if (H->ev_in) (void)hipEventDestroy(H->ev_in);
     if (H->ev_out) (void)hipEventDestroy(H->ev_out);
     delete h;

@@ -172,6 +172,29 @@ def test_duct32_cycle_variants(mode, env, monkeypatch):
     say("   iters", st["iters"], st["inner_iters_total"], "res", rr, "err", err, "ms", st["solve_ms"])
 
 
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("shape", [(64, 32, 32), (64, 22, 16), (16, 10, 6)])  # (nz, ny, nx)
+def test_one_pass_setup_equals_separate_passes(mode, shape, monkeypatch):
+    """The set-up's single pass over the density (the handle's density copies,
+    the finest 1/D and the first coarse level's face weights, and the density's
+    validation) forms every value as the separate passes do: the same solve, bit
+    for bit, with either (PP_ONEPASS=0 selects the separate passes)."""
+    nz, ny, nx = shape
+    case = W.random_small_case(11, nx, ny, nz)
+    say("one-pass set-up", mode, shape)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("PP_ONEPASS", flag)
+        with ppsolve.Solver(nx, ny, nz, case.h, mode=mode, tol=1e-10) as S:
+            S.set_density(rho_t)
+            p, st = S.solve(b_t)
+            out.append((cpu(p), st["iters"], st["rel_residual"]))
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    assert np.array_equal(out[0][0], out[1][0])
+    check_solution(rho_ref, b_ref, case.h, out[0][0], 1e-10)
+
+
 @pytest.mark.parametrize("scale", [1e-6, 1e6])
 def test_density_scale_far_from_one_refined(scale, monkeypatch):
     """Density times s: every face coefficient is divided by s, so the pressure is
