@@ -1715,14 +1715,15 @@ static double prepare_rhs(Handle* H, const double* rhs)
     k_sum_check<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, 0, red(H, G_BSUM, G_BBAD));
     check_launch();
     finish(H, red_host(H, G_BSUM, G_BBAD), lin_grid(n0), 2);
-    fetch_slots(H, G_BSUM, 2);
-    if (H->host_slots[G_BBAD] != 0.0)
-        throw Fail(PP_ERR_NONFINITE, "rhs has " + std::to_string((long long)H->host_slots[G_BBAD]) + " non-finite entries");
+    // the shift reads the mean from the device slot; the count of non-finite entries is checked
+    // with ||f|| after it (one wait for the host instead of two)
     k_shift_scale<<<lin_grid(n0), kBlock, 0, H->stream>>>((int)n0, rhs, H->f64, -cfg.h * cfg.h, coef(H, G_BSUM, -1, 1.0 / (double)n0),
                                                           1, red(H, G_FN2));
     check_launch();
     finish(H, red_host(H, G_FN2), lin_grid(n0), 1);
-    fetch_slots(H, G_FN2, 1);
+    fetch_slots(H, G_BSUM, G_FN2 - G_BSUM + 1);
+    if (H->host_slots[G_BBAD] != 0.0)
+        throw Fail(PP_ERR_NONFINITE, "rhs has " + std::to_string((long long)H->host_slots[G_BBAD]) + " non-finite entries");
     return std::sqrt(H->host_slots[G_FN2]);
 }
 
