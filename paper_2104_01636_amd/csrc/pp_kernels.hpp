@@ -78,7 +78,13 @@ struct Coefs {
     const double* s;   // slot array
     int num, den;      // factor = sign * s[num] / s[den]   (den < 0: factor = sign * s[num])
     double sign;
-    __device__ inline double get() const { return den < 0 ? sign * s[num] : sign * s[num] / s[den]; }
+    int c1 = -1, c2 = -1;  // with c1 >= 0 the numerator is s[num] + cs * s[c1] * s[c2]
+    double cs = 0.0;
+    __device__ inline double get() const
+    {
+        const double nv = c1 >= 0 ? s[num] + cs * s[c1] * s[c2] : s[num];
+        return den < 0 ? sign * nv : sign * nv / s[den];
+    }
 };
 
 __device__ inline int cell(int nx, int ny, int i, int j, int k) { return i + nx * (j + ny * k); }
@@ -199,8 +205,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_first(LevelView<T> L, const T
 }
 
 // One SOR half-sweep over one colour, in place.  With NDOT > 0 the launch also
-// reduces sum(x) (and <x, q> for NDOT >= 2, <x, f> for NDOT = 3) over all cells
-// after the update.
+// reduces sum(x) (and <x, q> for NDOT >= 2, <x, f> for NDOT >= 3, sum(f) for
+// NDOT = 4) over all cells after the update.
 template <class T, int NDOT, class TQ = T>
 __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T* __restrict__ f, T* x, int colour, int kper,
                                                        const TQ* __restrict__ q, Reduce R, T omega)
@@ -223,6 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_half(LevelView<T> L, const T*
             if constexpr (NDOT >= 1) acc[0] += (double)xv;
             if constexpr (NDOT >= 2) acc[1] += (double)xv * (double)q[c];
             if constexpr (NDOT >= 3) acc[2] += (double)xv * (double)f[c];
+            if constexpr (NDOT >= 4) acc[3] += (double)f[c];
         }
     }
     if constexpr (NDOT > 0) reduce_finish<NDOT>(acc, R);
@@ -328,10 +335,13 @@ template <> struct Vec2<double> { using type = double2; };
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_update_xr(int n, T* __restrict__ x, const T* __restrict__ d, T* __restrict__ r,
                                                      const T* __restrict__ q, Coefs alpha, int first, int skip_r, int want_red,
-                                                     Reduce R, float* __restrict__ r32, int do_x)
+                                                     Reduce R, float* __restrict__ r32, int do_x,
+                                                     double* __restrict__ alpha_out = nullptr)
 {
     using V = typename Vec2<T>::type;
-    const T a = (T)alpha.get();
+    const double ad = alpha.get();
+    const T a = (T)ad;
+    if (alpha_out && blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = ad;  // for the deferred x update
     double acc[2] = {0.0, 0.0};
     const int np = n >> 1;
     const int stride = gridDim.x * blockDim.x;

@@ -322,7 +322,7 @@ struct OpFirstR {
 };
 
 template <class T, int NDOT, class TQ>
-struct OpHalf {  // one colour of a red-black SOR sweep in place; dots sum(x), <x, q>, <x, f> (NDOT 1-3)
+struct OpHalf {  // one colour of a red-black SOR sweep in place; dots sum(x), <x, q>, <x, f>, sum(f) (NDOT 1-4)
     const T* f;
     T* x;
     const TQ* q;
@@ -346,6 +346,7 @@ struct OpHalf {  // one colour of a red-black SOR sweep in place; dots sum(x), <
         if constexpr (NDOT >= 1) acc[0] += (double)xv;
         if constexpr (NDOT >= 2) acc[1] += (double)xv * (double)e.q;
         if constexpr (NDOT >= 3) acc[2] += (double)xv * (double)e.f;
+        if constexpr (NDOT >= 4) acc[3] += (double)e.f;
     }
 };
 
@@ -580,7 +581,7 @@ struct OpFirstRestrict {
 // it and those need the prolongated red values around them, so the march runs
 // with overlapped tiles (OVL) and the red update trails the black one by a plane,
 // as in OpFirstRestrict.  Writes z = y on black cells and the updated red cells;
-// dots sum(z), <z, q> and <z, f> (NDOT 1-3) over the block's own cells.
+// dots sum(z), <z, q>, <z, f> and sum(f) (NDOT 1-4) over the block's own cells.
 template <class T, int NDOT, class TQ>
 struct OpProlongHalf {
     const T *f, *x, *e;
@@ -628,6 +629,7 @@ struct OpProlongHalf {
             if constexpr (NDOT >= 1) acc[0] += (double)zv;
             if constexpr (NDOT >= 2) acc[1] += (double)zv * (double)qm1;
             if constexpr (NDOT >= 3) acc[2] += (double)zv * (double)fm1;
+            if constexpr (NDOT >= 4) acc[3] += (double)fm1;
         }
         ym2 = ym1;
         ym1 = yv;

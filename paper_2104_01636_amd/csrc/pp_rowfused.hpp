@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(64 * BY) r_first_restrict(LevelView<float> L, 
 // y = x + wc P e on red cells, black cells one SOR update from them, then one
 // plane behind the red cells one SOR update from their black neighbours'
 // new values: z (black cells keep y).  NDOT dots over the block's own cells:
-// sum(z), <z, q> and <z, f>.  CPT even (the parents of a lane's cells are whole).
+// sum(z), <z, q>, <z, f> and sum(f).  CPT even (the parents of a lane's cells are whole).
 template <int CPT, int BY, int NDOT, class TQ>
 __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, const float* __restrict__ f,
                                                          const float* __restrict__ x, const float* __restrict__ ec,
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, co
     }
     float ym2[CPT] = {}, ym1[CPT] = {};  // y at the planes two and one below
     float fr[HP], ws6[HP][6];            // red cells one plane below: f and weights w, e, s, n, b, t
-    float fm1[CPT] = {};                 // f one plane below (NDOT 3)
+    float fm1[CPT] = {};                 // f one plane below (NDOT >= 3)
     double acc[NDOT > 0 ? NDOT : 1] = {};
     In Rg[2];
     fetch(Rg[0], vlo);
@@ -464,6 +464,7 @@ __global__ void __launch_bounds__(64 * BY) r_prolong_half(LevelView<float> L, co
                     if constexpr (NDOT >= 1) acc[0] += (double)zv[e];
                     if constexpr (NDOT >= 2) acc[1] += (double)zv[e] * (double)S.q[e];
                     if constexpr (NDOT >= 3) acc[2] += (double)zv[e] * (double)fm1[e];
+                    if constexpr (NDOT >= 4) acc[3] += (double)fm1[e];
                 }
             }
         }

@@ -157,13 +157,14 @@ static dim3 lin_grid(size_t n)
 // ---------------------------------------------------------------- slots
 
 enum : int {
-    kLevSlots = 8,      // per level: ZQ, SUMZ, DQ0, DQ1, DR, RR, RSUM, DR1
+    kLevSlots = 8,      // per level: ZQ, SUMZ, DQ0, DQ1, DR, RR, RSUM
     S_ZQ = 0, S_SUMZ = 1, S_DQ0 = 2, S_DQ1 = 3, S_DR = 4, S_RR = 5, S_RSUM = 6,
-    S_DR1 = 7,          // (the finest level's step-length numerators alternate between DR and DR1)
     G_BASE = 200,
     G_BSUM = G_BASE + 0, G_BBAD = G_BASE + 1, G_FN2 = G_BASE + 2, G_TRR = G_BASE + 3, G_TRSUM = G_BASE + 4,
     G_XSUM = G_BASE + 5, G_XBAD = G_BASE + 6, G_SCALE = G_BASE + 7, G_INVSCALE = G_BASE + 8, G_RHOSUM = G_BASE + 9,
     G_RHOBAD = G_BASE + 10, G_ONE = G_BASE + 11, G_ZERO = G_BASE + 12,
+    G_ALPHA0 = G_BASE + 13, G_ALPHA1 = G_BASE + 14,  // the finest level's step lengths, by step parity
+    G_FSUM = G_BASE + 15,                            // sum of the residual the finest cycle read
     kSlots = 256
 };
 static inline int lslot(int l, int s) { return l * kLevSlots + s; }
@@ -297,7 +298,8 @@ struct Handle {
     Params prm;
     std::string err = "no error";
     bool have_density = false;
-    int zr_slot = 0;               // slot of <z, f> for a cycle's third dot (ndot 3)
+    int zr_slot = 0;               // slots of <z, f> and sum(f) for a cycle's third and fourth dots (ndot 4)
+    int fsum_slot = 0;
 
     // geometry of levels
     std::vector<int> lnx, lny, lnz;
@@ -1151,7 +1153,7 @@ static dim3 launch_dir(Handle* H, const LevelView<T>& v, const TZ* z, const T* d
 template <class T, class TQ>
 static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int colour, int ndot, const TQ* q, int l)
 {
-    Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ), H->zr_slot);
+    Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ), H->zr_slot, H->fsum_slot);
     dim3 grid;
     {
         // reads x, f and the weights (or the density; the per-cell kernels also 1/D); writes one
@@ -1162,7 +1164,7 @@ static void smooth_half(Handle* H, Lev<T>& V, bool fine, const T* f, T* x, int c
         if (ndot == 0) grid = launch_half<T, 0, TQ>(H, V.v, f, x, colour, q, R);
         else if (ndot == 1) grid = launch_half<T, 1, TQ>(H, V.v, f, x, colour, q, R);
         else if (ndot == 2) grid = launch_half<T, 2, TQ>(H, V.v, f, x, colour, q, R);
-        else grid = launch_half<T, 3, TQ>(H, V.v, f, x, colour, q, R);
+        else grid = launch_half<T, 4, TQ>(H, V.v, f, x, colour, q, R);
     }
     if (ndot > 0) finish(H, R, grid, ndot);
 }
@@ -1243,8 +1245,8 @@ static void cycle_pre(Handle* H, Lev<T>& V, int l, int nu, const T* f, T* x, T* 
 // Up leg of a cycle at level l: y = x + wc P e (injection), then nu sweeps
 // (black, then red) of K y = f, the first black half-sweep fused with the
 // prolongation (and, on a fused level, the red one too).  ndot: 0 none,
-// 1 sum(y), 2 sum(y) and <y, q>, 3 also <y, f> (into H->zr_slot), reduced on the
-// last half-sweep into level l's slots.  Returns y.
+// 1 sum(y), 2 sum(y) and <y, q>, 4 also <y, f> and sum(f) (into H->zr_slot and
+// H->fsum_slot), reduced on the last half-sweep into level l's slots.  Returns y.
 template <class T, class TQ>
 static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x, const T* e, T wc, T* y, int ndot,
                      const TQ* q)
@@ -1253,7 +1255,7 @@ static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x
     if (nu == 1 && H->prm.pfuse && fused(H, sizeof(T), V.n)) {
         // reads x, f, the weights (or the density), the coarse correction and q for the dot;
         // writes z
-        const Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ), H->zr_slot);
+        const Reduce R = red(H, lslot(l, S_SUMZ), lslot(l, S_ZQ), H->zr_slot, H->fsum_slot);
         dim3 grid;
         {
             TimeScope ts(H, fine ? kid<T>(KT_PROLONG_HALF) : -1,
@@ -1261,7 +1263,7 @@ static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x
             if (ndot == 0) grid = launch_prolong_half<T, 0, TQ>(H, V.v, f, x, e, wc, y, q, R);
             else if (ndot == 1) grid = launch_prolong_half<T, 1, TQ>(H, V.v, f, x, e, wc, y, q, R);
             else if (ndot == 2) grid = launch_prolong_half<T, 2, TQ>(H, V.v, f, x, e, wc, y, q, R);
-            else grid = launch_prolong_half<T, 3, TQ>(H, V.v, f, x, e, wc, y, q, R);
+            else grid = launch_prolong_half<T, 4, TQ>(H, V.v, f, x, e, wc, y, q, R);
         }
         if (ndot > 0) finish(H, R, grid, ndot);
         return y;
@@ -1282,8 +1284,9 @@ static T* cycle_post(Handle* H, Lev<T>& V, int l, int nu, const T* f, const T* x
 
 
 // One multigrid cycle at level l for right-hand side f; returns the buffer holding
-// the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, 3 also <z, f> (into
-// H->zr_slot), reduced on the last half-sweep into level l's slots.
+// the result.  ndot: 0 none, 1 sum(z), 2 sum(z) and <z, q>, 4 also <z, f> and
+// sum(f) (into H->zr_slot and H->fsum_slot), reduced on the last half-sweep into
+// level l's slots.
 template <class T, class TQ = T>
 static T* mgcycle(Handle* H, Hier<T>& Hh, int l, const T* f, int ndot, const TQ* q, const Fold<T>* fold = nullptr)
 {
@@ -1480,16 +1483,17 @@ static dim3 fine_grid(const Handle* H, size_t n)
 
 // One step of the finest-level flexible CG, float64 throughout (x, r, d, q and
 // the operator from rho), preconditioned by one multigrid cycle in precision P:
-// z = M r (the cycle also reduces sum(z), <z, q_old> and <z, r>), d = (z - mean z)
-// + beta d_old, q = K d with <d, q>, then r -= alpha q (and the float32 copy of r
-// for a float32 cycle) with ||r||^2, alpha = <z, r> / <d, q>.  <z, r> equals
-// <d, r> up to rounding (r is orthogonal to d_old after the previous step and
-// sums to zero), so the direction update need not read r.  The cycle's r is the
-// float32 copy in the refined form.  The x update is deferred: step k applies
-// x += alpha_{k-1} d_{k-1} while it reads d_{k-1} anyway, and fcg() applies the
-// last one.  The numerators <z, r> of consecutive steps alternate between two
-// slots (step k's cycle writes its own before step k's direction update reads
-// step k-1's).
+// z = M r (the cycle also reduces sum(z), <z, q_old>, <z, r> and sum(r)),
+// d = (z - mean z) + beta d_old, q = K d with <d, q>, then r -= alpha q (and the
+// float32 copy of r for a float32 cycle) with ||r||^2, where
+// alpha = (<z, r> - mean(z) sum(r)) / <d, q>: the numerator is <d, r> without its
+// beta <d_old, r> term, which the previous step's alpha makes zero up to
+// rounding, so the direction update need not read r.  (The mean term is kept:
+// z may carry a large constant, and near the rounding floor mean(z) sum(r) is
+// not small against <z, r>.)  The cycle's r is the float32 copy in the refined
+// form.  The x update is deferred: step k applies x += alpha_{k-1} d_{k-1} while
+// it reads d_{k-1} anyway, and fcg() applies the last one; the r update stores
+// its alpha, by step parity, for that.
 template <class P>
 static void krylov_step(Handle* H, Hier<P>& Hh, int k)
 {
@@ -1497,11 +1501,12 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
     const size_t n0 = (size_t)cfg.nx * cfg.ny * cfg.nz;
     const int dq_prev = lslot(0, (k & 1) ? S_DQ0 : S_DQ1);
     const int dq_cur = lslot(0, (k & 1) ? S_DQ1 : S_DQ0);
-    const int zr_prev = lslot(0, (k & 1) ? S_DR : S_DR1);
-    const int zr_cur = lslot(0, (k & 1) ? S_DR1 : S_DR);
+    const int a_prev = (k & 1) ? G_ALPHA0 : G_ALPHA1;
+    const int a_cur = (k & 1) ? G_ALPHA1 : G_ALPHA0;
     // the first step has no q_old: its <z, q> (unused) is taken against r instead
-    H->zr_slot = zr_cur;
-    P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, 3, k > 0 ? H->q64 : H->r64);
+    H->zr_slot = lslot(0, S_DR);
+    H->fsum_slot = G_FSUM;
+    P* z = mgcycle<P, double>(H, Hh, 0, Hh.L[0].rhs, 4, k > 0 ? H->q64 : H->r64);
     {
         const LevelView<double> v = fine64(H);
         const Reduce R = red(H, dq_cur);
@@ -1514,18 +1519,22 @@ static void krylov_step(Handle* H, Hier<P>& Hh, int k)
             grid = launch_dir<double, P, true>(H, v, z, H->d, H->d2, H->q64, H->r64, H->x64,
                                                coef(H, lslot(0, S_ZQ), dq_prev, -1.0), k > 0,
                                                coef(H, lslot(0, S_SUMZ), -1, 1.0 / (double)n0), 1,
-                                               coef(H, zr_prev, dq_prev, 1.0), R);
+                                               coef(H, a_prev, -1, 1.0), R);
         }
         finish(H, R, grid, 1);
     }
     {
         const Reduce R = red_host(H, lslot(0, S_RR), lslot(0, S_RSUM));
+        Coefs alpha = coef(H, lslot(0, S_DR), dq_cur, 1.0);
+        alpha.c1 = lslot(0, S_SUMZ);
+        alpha.c2 = G_FSUM;
+        alpha.cs = -1.0 / (double)n0;
         {
             // reads r and q; writes r and the float32 copy of r
             TimeScope ts(H, kid<double>(KT_UPDATE_XR), (double)n0 * (24.0 + (H->r32 ? 4.0 : 0.0)));
             k_update_xr<double><<<fine_grid(H, n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d2, H->r64, H->q64,
-                                                                          coef(H, zr_cur, dq_cur, 1.0), 0, 0, 1, R,
-                                                                          H->r32, 0);
+                                                                          alpha, 0, 0, 1, R, H->r32, 0,
+                                                                          H->slots + a_cur);
             check_launch();
         }
         finish(H, R, fine_grid(H, n0), 2);
@@ -1599,7 +1608,7 @@ static int fcg(Handle* H, Hier<P>& Hh, double rnorm_stop, int max_it, double* rn
     if (k > 0) {  // the deferred x += alpha d of the last step
         const size_t n0 = (size_t)H->cfg.nx * H->cfg.ny * H->cfg.nz;
         const int last = k - 1;
-        const Coefs a = coef(H, lslot(0, (last & 1) ? S_DR1 : S_DR), lslot(0, (last & 1) ? S_DQ1 : S_DQ0), 1.0);
+        const Coefs a = coef(H, (last & 1) ? G_ALPHA1 : G_ALPHA0, -1, 1.0);
         k_update_xr<double><<<fine_grid(H, n0), kBlock, 0, H->stream>>>((int)n0, H->x64, H->d, H->r64, H->q64, a, 0, 1, 0,
                                                                     red(H, G_FN2), (float*)nullptr, 1);
         check_launch();

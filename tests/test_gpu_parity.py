@@ -195,6 +195,39 @@ def test_one_pass_setup_equals_separate_passes(mode, shape, monkeypatch):
     check_solution(rho_ref, b_ref, case.h, out[0][0], 1e-10)
 
 
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("name", ["duct32", "bubble48"])
+def test_tight_tolerance_near_the_rounding_floor(mode, name):
+    """Close to the rounding floor the finest-level step length stays accurate:
+    its numerator <z, r> - mean(z) sum(r) is <d, r> without the term that the
+    previous step's length makes zero, and keeps the mean term, which is not
+    small against <z, r> once r is near rounding level.  The solve reaches 1e-13
+    on the duct and 1e-12 on the static bubble (whose float64 floor is about
+    4.5e-13 with either numerator) instead of stalling at max_iters, and the
+    oracle's operator agrees on the residual."""
+    if name == "duct32":
+        case = W.preset("duct32")
+        rho_ref, b_ref, rho_t, b_t = inputs(case)
+        nx, ny, nz, h = case.nx, case.ny, case.nz, case.h
+    else:
+        nx, ny, nz = 48, 48, 64
+        h = 1.0 / nx
+        a = W.volume_fraction(nx, ny, nz, np.array([[24.3, 23.6, 31.1]]), 19.0)
+        rho_ref = P.density_from_fraction(a)
+        b_ref = P.surface_tension_rhs(rho_ref, a, 2.0 / (9.5 * h), 0.072, h)
+        rho_t, b_t = gpu(rho_ref), gpu(b_ref)
+    tol = 1e-13 if name == "duct32" else 1e-12
+    say("tight tolerance", name, mode, tol)
+    with ppsolve.Solver(nx, ny, nz, h, mode=mode, tol=tol, max_iters=300) as S:
+        S.set_density(rho_t)
+        p, st = S.solve(b_t)
+    p = cpu(p)
+    rr = cref.relative_residual(rho_ref, b_ref, p, h)
+    say("   iters", st["iters"], "res", st["rel_residual"], "oracle res", rr)
+    assert st["rel_residual"] <= tol and st["iters"] < 100
+    assert rr <= 2 * tol
+
+
 @pytest.mark.parametrize("scale", [1e-6, 1e6])
 def test_density_scale_far_from_one_refined(scale, monkeypatch):
     """Density times s: every face coefficient is divided by s, so the pressure is
