@@ -265,8 +265,8 @@ struct Params {
     int rwblocks = 512;         // blocks of a finest-level row-wave launch, at most (z split to reach it),
     int rwrows = 8;             // rows per block (4 or 8) and band order, one wavefront per row
     int rwsblocks = 256;        // the same with split rows (rows 4, 6 or 8), measured best at 256 blocks
-    int rwsrows = 4;            // of 4 rows in the plain band order (366 us; 8 rows 448, 384 blocks 453)
-    int rwsxcd = 0;
+    int rwsrows = 4;            // of 4 rows in the XCD band order (the direction update 312 us; plain
+    int rwsxcd = 1;             // order 317, 8 rows 327-332, 6 rows 351, 512 blocks 321)
     int eblocks = 512;          // blocks of the finest-level r/q update, at most (164 us with 512, 185
                                 // with 2048, 215 with 256)
     bool onepass = true;        // the finest level's set-up and the first coarse level's weights in one
