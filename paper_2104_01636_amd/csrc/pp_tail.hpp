@@ -389,17 +389,13 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
     // the dense inverse's entries this thread multiplies on the last level (see
     // below), loaded now so that their latency overlaps the staging
     constexpr int kPer = kTailDenseMax / kTailDenseSplit;
-    constexpr bool kEarly = true;
     const int dr = threadIdx.x % kTailDenseMax, dc0 = (threadIdx.x / kTailDenseMax) * kPer;
     T m[kPer];
-    auto load_m = [&]() {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int c = dc0 + u;
-            m[u] = (dr < D.nd && c < D.nd) ? ldg(D.Minv, c * D.nd + dr) : T(0);
-        }
-    };
-    if constexpr (kEarly) load_m();
+    for (int u = 0; u < kPer; ++u) {
+        const int c = dc0 + u;
+        m[u] = (dr < D.nd && c < D.nd) ? ldg(D.Minv, c * D.nd + dr) : T(0);
+    }
 
     // stage the operators of the later levels (and, with LDS0, the first level's
     // operator and right-hand side after them): every load of the cycle but the
@@ -524,7 +520,6 @@ __global__ void __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_
             // over one chunk of the columns, with all of its loads issued together;
             // the chunks are then added in a fixed order
             const int nd = D.nd;
-            if constexpr (!kEarly) load_m();
             T acc = T(0);
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
