@@ -1694,7 +1694,10 @@ static void set_density(Handle* H, const double* rho)
     }
     if (H->M64) {
         // after the coarsest weights (and every use of the previous inverse: the same stream) on
-        // the second stream; the next solve waits for it before its first cycle
+        // the second stream; the next solve waits for it before its first cycle.  A set-up that
+        // follows before any solve may rewrite the weights a previous inverse is still reading;
+        // that inverse's result is then overwritten by this one, queued after it on the same
+        // stream, and nothing reads the matrix in between
         const int l = nl - 1;
         PP_HIP(hipEventRecord(H->ev_coarse, H->stream));
         PP_HIP(hipStreamWaitEvent(H->side, H->ev_coarse, 0));
