@@ -196,6 +196,37 @@ def test_one_pass_setup_equals_separate_passes(mode, shape, monkeypatch):
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
+def test_back_to_back_set_ups_then_solve(mode):
+    """The coarsest level's dense inverse is formed on a second stream and the
+    next solve waits for it.  Two set-ups in a row (the second while the first
+    one's inverse may still run) and then a solve give, bit for bit, the solve
+    of a handle that only saw the second density; a solve right after a set-up
+    on a handle that has solved before does too."""
+    case = W.preset("duct32")
+    other = W.random_small_case(3, case.nx, case.ny, case.nz)
+    say("back-to-back set-ups", mode)
+    rho_ref, b_ref, rho_t, b_t = inputs(case)
+    rho_o = ppsolve.density_from_fraction(gpu(other.alpha))
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=1e-10) as S:
+        S.set_density(rho_t)
+        p_fresh, st_fresh = S.solve(b_t)
+        p_fresh = cpu(p_fresh)
+    with ppsolve.Solver(case.nx, case.ny, case.nz, case.h, mode=mode, tol=1e-10) as S:
+        S.set_density(rho_o)
+        S.set_density(rho_t)
+        p_two, st_two = S.solve(b_t)
+        p_two = cpu(p_two)
+        S.set_density(rho_o)
+        S.solve(b_t)
+        S.set_density(rho_t)
+        p_again, _ = S.solve(b_t)
+        p_again = cpu(p_again)
+    assert st_two["iters"] == st_fresh["iters"]
+    assert np.array_equal(p_two, p_fresh) and np.array_equal(p_again, p_fresh)
+    check_solution(rho_ref, b_ref, case.h, p_fresh, 1e-10)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_refined"])
 @pytest.mark.parametrize("name", ["duct32", "bubble48"])
 def test_tight_tolerance_near_the_rounding_floor(mode, name):
     """Close to the rounding floor the finest-level step length stays accurate:
